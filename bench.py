@@ -1,0 +1,269 @@
+"""Benchmark of the RBE k-space force on one MI355X.
+
+A step is one whole evaluation of the hot path on the 1,000,000-atom
+water + 1 mol/L NaCl box (alpha = 0.06 / A^2, P = 100 wave vectors):
+  draw P wave vectors on the device -> rho(k) pass -> cross-tile reduction ->
+  force/energy pass.
+Inputs are resident in HBM before timing starts; nothing is skipped inside
+the timed region.  The headline value is the FP32-mixed form in
+G(particle*k)/s (N * P terms per evaluation); the FP64 form, the phase-cache
+variant, P = 200, the adjoint and the batched 128-replica form are timed
+beside it and reported in the same JSON line.
+
+roofline: VALU issue slots.  Algorithmic work per (particle, k) term, per
+kernel: rho pass 5 FMA-class ops + sin + cos; force pass 8 FMA-class ops +
+sin + cos.  On gfx950 v_sin_f32 / v_cos_f32 issue at half rate (2 slots,
+measured), other VALU ops at 1 slot.  Peak = 256 CU x 64 lanes x 2.4 GHz =
+39.32e12 lane-slots/s (packed FP32 is not used).
+
+cpu_baseline: the FP64 oracle (plain C, OpenMP over independent outputs) on
+the same box, the same system and the same wave vectors, repeated for about
+10 s; it also gives the stated error of each GPU form.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_SLOTS = 256 * 64 * 2.4e9          # VALU lane-slots per second
+SLOTS_RHO = 5 + 2 * 2                  # per term: 5 FMA-class + sin + cos (2 slots each)
+SLOTS_FORCE = 8 + 2 * 2
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--quick", action="store_true", help="skip the extra forms and the CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+class Timer:
+    """HIP events on torch's current stream (the stream every library call is enqueued on)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.events = []
+
+    def mark(self):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record()
+        self.events.append(e)
+        return e
+
+
+def run_form(torch, plan_cls, batch_cls, X, L, alpha, P, precision, phase_mode, steps, warmup, seed=2003):
+    from paper_2407_09315_amd import Batch, Plan  # noqa: F401
+    n = X[0].numel()
+    plan = plan_cls(batch_cls.single(n, P, L, alpha), precision=precision, phase_mode=phase_mode)
+    m, w = plan.sample_k_device(seed, 0)
+    rho = torch.empty((P, 2), dtype=torch.float64, device=X[0].device)
+    F = torch.empty((3, n), dtype=plan.force_dtype, device=X[0].device)
+    U = torch.empty(1, dtype=torch.float64, device=X[0].device)
+
+    def step(k, ev=None):
+        plan.sample_k_device(seed, k, m, w)
+        if ev is not None:
+            ev.append(torch.cuda.Event(enable_timing=True))
+            ev[-1].record()
+        plan.structure_factor(*X, m, rho)
+        if ev is not None:
+            ev.append(torch.cuda.Event(enable_timing=True))
+            ev[-1].record()
+        plan.kspace_force(*X, m, w, rho, F, U)
+        if ev is not None:
+            ev.append(torch.cuda.Event(enable_timing=True))
+            ev[-1].record()
+
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(warmup + k)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    # per-kernel durations, measured in a second pass so the events do not perturb the wall time
+    ev = []
+    for k in range(steps):
+        step(warmup + k, ev)
+    torch.cuda.synchronize()
+    t_rho = np.mean([ev[3 * i].elapsed_time(ev[3 * i + 1]) for i in range(steps)]) * 1e-3
+    t_force = np.mean([ev[3 * i + 1].elapsed_time(ev[3 * i + 2]) for i in range(steps)]) * 1e-3
+    # the result of the first timed step's wave vectors, for the error statement
+    plan.sample_k_device(seed, warmup, m, w)
+    plan.structure_factor(*X, m, rho)
+    plan.kspace_force(*X, m, w, rho, F, U)
+    torch.cuda.synchronize()
+    return {"wall_s": wall, "t_rho_s": float(t_rho), "t_force_s": float(t_force),
+            "m": m.cpu().numpy(), "w": w.cpu().numpy(), "F": F.double().cpu().numpy(),
+            "U": float(U.cpu()[0]), "rho": rho.cpu().numpy()}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(multi-GPU sharding is a design note only)"}))
+        sys.exit(2)
+    import torch
+
+    import rbe_inputs as ri
+    from paper_2407_09315_amd import Batch, Plan
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t_gen = time.perf_counter()
+    s, alpha, P = ri.c3a_electrolyte()
+    log(f"generated {s.name} (N={s.n}, L={s.L:.4f}) in {time.perf_counter() - t_gen:.1f}s")
+    X = [torch.tensor(a, dtype=torch.float64, device=dev) for a in (s.x, s.y, s.z, s.q)]
+    terms = s.n * P
+
+    res = {}
+    res["fp32"] = run_form(torch, Plan, Batch, X, s.L, alpha, P, "fp32_mixed", "recompute", args.steps, args.warmup)
+    log(f"fp32_mixed: {res['fp32']['wall_s'] * 1e3:.3f} ms/step")
+    res["fp64"] = run_form(torch, Plan, Batch, X, s.L, alpha, P, "fp64", "recompute", args.steps, args.warmup)
+    log(f"fp64: {res['fp64']['wall_s'] * 1e3:.3f} ms/step")
+    extra = {}
+    if not args.quick:
+        r = run_form(torch, Plan, Batch, X, s.L, alpha, P, "fp32_mixed", "cached", max(5, args.steps // 5), 3)
+        extra["fp32_mixed_cached_phase_P100"] = {"ms_per_step": r["wall_s"] * 1e3, "G_terms_per_s": terms / r["wall_s"] / 1e9,
+                                                 "rho_call_ms": r["t_rho_s"] * 1e3, "force_call_ms": r["t_force_s"] * 1e3}
+        log("cached done")
+        for prec, key in (("fp32_mixed", "fp32_mixed_P200"), ("fp64", "fp64_P200")):
+            r = run_form(torch, Plan, Batch, X, s.L, alpha, 200, prec, "recompute", max(5, args.steps // 5), 3)
+            extra[key] = {"ms_per_step": r["wall_s"] * 1e3, "G_terms_per_s": s.n * 200 / r["wall_s"] / 1e9}
+        log("P200 done")
+        extra.update(bench_vjp(torch, ri, Plan, Batch, dev, max(5, args.steps // 5)))
+        log("vjp done")
+        extra.update(bench_batched(torch, ri, Plan, Batch, dev, max(5, args.steps // 5)))
+        log("batched done")
+
+    f32, f64 = res["fp32"], res["fp64"]
+    value = terms / f32["wall_s"] / 1e9
+    dom = "rho" if f32["t_rho_s"] >= f32["t_force_s"] else "force"
+    t_dom = f32["t_rho_s"] if dom == "rho" else f32["t_force_s"]
+    slots = SLOTS_RHO if dom == "rho" else SLOTS_FORCE
+    achieved = slots * terms / t_dom / 1e12
+    peak = PEAK_SLOTS / 1e12
+    out = {
+        "metric": "RBE force G(particle·k)/s & ms/eval at 1M, FP32-mixed vs FP64 at stated err",
+        "value": round(value, 3),
+        "unit": "G(particle·k)/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f32["wall_s"] * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "water+1M NaCl electrolyte, N=1,000,000, L=217.0535 A, alpha=0.06, P=100",
+                   "N": s.n, "P": P, "L": s.L, "alpha": alpha, "precision": "fp32_mixed",
+                   "phase_mode": "recompute", "step": "device sampling + rho pass + reduction + force pass"},
+        "fp64": {"ms_per_step": round(f64["wall_s"] * 1e3, 4), "G_terms_per_s": round(terms / f64["wall_s"] / 1e9, 3),
+                 "rho_call_ms": round(f64["t_rho_s"] * 1e3, 4), "force_call_ms": round(f64["t_force_s"] * 1e3, 4)},
+        "fp32_over_fp64_speedup": round(f64["wall_s"] / f32["wall_s"], 3),
+        "fp32_calls_ms": {"rho_call": round(f32["t_rho_s"] * 1e3, 4), "force_call": round(f32["t_force_s"] * 1e3, 4)},
+        "roofline": {"bound": "alu", "kernel": "rho_f32_kernel (+reduce)" if dom == "rho" else "force_f32_kernel",
+                     "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "ops_per_term": slots, "terms_per_launch": terms},
+        "extra": extra,
+    }
+    if not args.quick and not args.no_cpu:
+        out["cpu_baseline"], out["error_vs_oracle"] = cpu_baseline(s, P, res)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(s, P, res):
+    import oracle
+    m, w = res["fp32"]["m"], res["fp32"]["w"]
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        F_ref, U_ref, rho_ref = oracle.force_energy(s.x, s.y, s.z, s.q, m, w, s.L)
+        reps += 1
+        if time.perf_counter() - t0 > 10.0 or reps >= 5:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    base = {"value": round(s.n * P / dt / 1e9, 5), "unit": "G(particle·k)/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": f"full evaluation (rho + F + U) of the same 1M-atom system and P={P} "
+                                        f"wave vectors, {reps} repetitions, {dt:.2f} s each"}
+    errs = {}
+    for key, prec in (("fp32", "fp32_mixed"), ("fp64", "fp64")):
+        r = res[key]
+        if not np.array_equal(r["m"], m):
+            F_ref2, U_ref2, rho_ref2 = oracle.force_energy(s.x, s.y, s.z, s.q, r["m"], r["w"], s.L)
+        else:
+            F_ref2, U_ref2, rho_ref2 = F_ref, U_ref, rho_ref
+        F = r["F"]
+        rc = r["rho"][:, 0] + 1j * r["rho"][:, 1]
+        errs[prec] = {"force_rel_rms": float(np.sqrt(np.sum((F - F_ref2) ** 2) / np.sum(F_ref2 ** 2))),
+                      "energy_rel": float(abs(r["U"] - U_ref2) / abs(U_ref2)),
+                      "rho_max_over_qnorm": float(np.max(np.abs(rc - rho_ref2)) / np.sqrt(np.sum(s.q ** 2)))}
+    return base, errs
+
+
+def bench_vjp(torch, ri, Plan, Batch, dev, steps):
+    s, alpha, P = ri.c4_differentiable()
+    X = [torch.tensor(a, dtype=torch.float64, device=dev) for a in (s.x, s.y, s.z, s.q)]
+    out = {}
+    for prec in ("fp32_mixed", "fp64"):
+        plan = Plan(Batch.single(s.n, P, s.L, alpha), precision=prec)
+        m, w = plan.sample_k_device(2005, 0)
+        F, U, rho = plan.forward(*X, m, w)
+        gF = torch.randn((3, s.n), device=dev, dtype=torch.float64).to(plan.force_dtype)
+        gU = torch.ones(1, dtype=torch.float64, device=dev)
+        gr, gq = plan.kspace_vjp(*X, m, w, rho, gU, gF)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            F, U, rho = plan.forward(*X, m, w)
+            plan.kspace_vjp(*X, m, w, rho, gU, gF, gr, gq)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[f"vjp_{prec}_N200k_P100"] = {"ms_forward_plus_backward": dt * 1e3,
+                                         "G_terms_per_s_4passes": 4 * s.n * P / dt / 1e9}
+    return out
+
+
+def bench_batched(torch, ri, Plan, Batch, dev, steps):
+    reps = ri.c5_replicas(B=128)
+    systems = reps.systems
+    batch = Batch.from_sizes([x.n for x in systems], [reps.P] * len(systems), [x.L for x in systems], reps.alphas)
+    plan = Plan(batch, precision="fp32_mixed")
+    cat = [torch.tensor(np.concatenate([getattr(x, a) for x in systems]), dtype=torch.float64, device=dev)
+           for a in ("x", "y", "z", "q")]
+    m, w = plan.sample_k_device(6000, 0)
+    for k in range(3):
+        plan.sample_k_device(6000, k, m, w)
+        plan.forward(*cat, m, w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        plan.sample_k_device(6000, k, m, w)
+        plan.forward(*cat, m, w)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    terms = sum(x.n for x in systems) * reps.P
+    return {"batched_128_replicas_fp32_mixed": {"ms_per_step": dt * 1e3, "G_terms_per_s": terms / dt / 1e9,
+                                                "N_total": int(sum(x.n for x in systems))}}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * rbe.h -- C ABI of the MI355X (gfx950) random batch Ewald k-space library.
+ *
+ * The library evaluates the Fourier-space (k-space) part of the Coulomb force
+ * for N point charges in a periodic cubic box with the random batch Ewald
+ * (RBE) estimator (arXiv 2407.09315, Sec. 2.2 and Algorithm 1):
+ *
+ *   wave vectors     k_l = 2 pi m_l / L,  m_l in Z^3 \ {0},  l = 1..P,
+ *                    drawn from exp(-k^2 / 4 alpha) / S      (Sec. 2.2; Alg. 1 step 1)
+ *   structure factor rho(k) = sum_j q_j exp(i k . r_j)       (Sec. 2.2; Alg. 1 steps 2-3)
+ *   force            F_i = -sum_l c_l q_i k_l Im(exp(-i k_l . r_i) rho(k_l))
+ *                                                           (Eq. frbe; Alg. 1 step 4)
+ *   energy           U   = sum_l (c_l / 2) |rho(k_l)|^2
+ *   with             c_l = w_l 4 pi / (V k_l^2),  V = L^3,
+ *                    w_l = S / P for the RBE estimator (Eq. frbe, Q = S),
+ *                    w_l = exp(-k_l^2 / 4 alpha) for the full Ewald sum (Eq. long).
+ *   S = (sum_{m in Z} exp(-pi^2 m^2 / (alpha L^2)))^3 - 1 is the normalisation
+ *   of the sampling density (the paper's Q).
+ *
+ * Units: Gaussian, prefactor 1 (energy in e^2/A for charges in e and lengths
+ * in A); the caller multiplies by its Coulomb constant.  No neutralising
+ * background term is added for non-neutral systems.
+ *
+ * Batches.  Every device call works on a batch of B independent systems whose
+ * particles and wave vectors are concatenated: system b owns particles
+ * [sys_off[b], sys_off[b+1]) and wave vectors [k_off[b], k_off[b+1]).  A single
+ * system is the batch B = 1; there is one code path.
+ *
+ * Memory.  (dev) = caller-owned device memory, (host) = caller-owned host
+ * memory.  The library never allocates or frees device memory: all scratch
+ * lives in a caller-provided workspace of rbe_plan_workspace_bytes() bytes,
+ * 256-byte aligned.  Its only allocation is the host-side plan object.
+ * Device work is enqueued asynchronously on `stream` (a hipStream_t; NULL is
+ * the default stream) and the call returns without synchronising.
+ *
+ * Layouts.  Positions and charges: four FP64 arrays x, y, z, q of N_total
+ * elements (structure of arrays).  Positions may lie anywhere; results are
+ * periodic in each coordinate with period L.  Wave vectors m: int32, P_total
+ * rows of (m_x, m_y, m_z).  rho: FP64 pairs (Re, Im), P_total rows.  Forces:
+ * three planes of N_total values, F[d * N_total + i], in FP64 (RBE_FP64) or
+ * FP32 (RBE_FP32_MIXED).  U: one FP64 value per system.
+ *
+ * Errors.  Every call returns an rbe_status.  Arguments are checked on the
+ * host before anything is enqueued; on failure nothing is launched and
+ * rbe_last_error() (thread-local) holds a message.  Nothing aborts.
+ * Non-finite inputs are not checked on the device and propagate as NaN.
+ *
+ * Determinism.  Every reduction runs in a fixed order, so results are
+ * bitwise reproducible for the same inputs, plan parameters and device.
+ */
+#ifndef RBE_H
+#define RBE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RBE_ABI_VERSION 1
+
+typedef enum {
+    RBE_OK = 0,
+    RBE_EINVAL = -1,          /* invalid argument (host-side check) */
+    RBE_ENODEV = -2,          /* no usable HIP device */
+    RBE_EHIP = -3,            /* a HIP runtime call or kernel launch failed */
+    RBE_EWORKSPACE = -4,      /* workspace missing, misaligned or too small */
+    RBE_EUNSUPPORTED = -5     /* valid request this build does not implement */
+} rbe_status;
+
+typedef enum {
+    RBE_FP64 = 0,             /* FP64 phases, sin/cos and sums throughout */
+    RBE_FP32_MIXED = 1        /* exact fixed-point phases, FP32 sin/cos and per-wave sums,
+                                 FP64 cross-block sums and energy; FP32 forces */
+} rbe_precision;
+
+typedef enum {
+    RBE_PHASE_AUTO = 0,       /* the measured choice for this shape (currently recompute) */
+    RBE_PHASE_RECOMPUTE = 1,  /* the force pass recomputes every phase */
+    RBE_PHASE_CACHED = 2      /* the rho pass stores (cos, sin) of every (i, l) in the
+                                 workspace (8 B per term, FP32_MIXED only) and the force
+                                 pass reads them */
+} rbe_phase_mode;
+
+typedef struct rbe_plan rbe_plan;   /* opaque; host memory owned by the library */
+
+/* ---------------------------------------------------------------- host-only calls */
+
+/*
+ * Draw P wave-vector index triples m (Sec. 2.2; Alg. 1 step 1): i.i.d. from
+ * exp(-k^2 / 4 alpha) with k = 2 pi m / L and m != 0.  Each component is a
+ * 1-D discrete Gaussian exp(-pi^2 m_d^2 / (alpha L^2)) drawn by inverse CDF on
+ * |m_d| <= ceil(9 L sqrt(alpha/2) / pi) + 1; a zero vector is redrawn.
+ * Uniforms come from Philox4x64-10 (Salmon et al., SC'11) with key
+ * (seed, stream_id) and counter (l, attempt, 0, 0); word d gives
+ * u_d = (word_d >> 11) * 2^-53.  m_out: (host) P*3 int32.  w_out (host, P
+ * doubles, may be NULL) receives S/P; S_out (host, may be NULL) receives S.
+ * Returns RBE_EINVAL for L <= 0, alpha <= 0, P < 0, NULL m_out with P > 0,
+ * or if the zero vector is drawn 1024 times in a row.
+ */
+rbe_status rbe_sample_k(uint64_t seed, uint64_t stream_id, double L, double alpha, int32_t P,
+                        int32_t *m_out, double *w_out, double *S_out);
+
+/* S = (sum_m exp(-pi^2 m^2 / (alpha L^2)))^3 - 1 (the paper's Q). */
+rbe_status rbe_normalization(double L, double alpha, double *S_out);
+
+/*
+ * Full-Ewald weights w_l = exp(-k_l^2 / 4 alpha) (Eq. long) for given m (host,
+ * P*3 int32) into w_out (host, P doubles).  With these weights the library
+ * evaluates the deterministic Ewald k-space sum over the listed vectors.
+ */
+rbe_status rbe_ewald_weights(double L, double alpha, int32_t P, const int32_t *m, double *w_out);
+
+/*
+ * Create a plan for B systems.  sys_off, k_off: (host) B+1 non-decreasing
+ * offsets starting at 0 (particles, wave vectors).  L, alpha: (host) B values
+ * each, > 0.  precision: rbe_precision; phase_mode: rbe_phase_mode.  The plan
+ * copies everything it needs; the arrays may be freed afterwards.  Tile
+ * parameters come from the built-in defaults or from rbe_plan_set_tiles.
+ */
+rbe_status rbe_plan_create(int32_t B, const int64_t *sys_off, const int64_t *k_off,
+                           const double *L, const double *alpha, int32_t precision,
+                           int32_t phase_mode, rbe_plan **out);
+
+/* Bytes of device workspace the plan needs (a multiple of 256). */
+size_t rbe_plan_workspace_bytes(const rbe_plan *plan);
+
+/*
+ * Select kernel variants (autotuner hook).  rho_variant and force_variant
+ * index the variant tables reported by rbe_plan_num_variants; -1 keeps the
+ * current choice.  Changes the workspace layout: query the size and upload
+ * again afterwards.
+ */
+rbe_status rbe_plan_set_tiles(rbe_plan *plan, int32_t rho_variant, int32_t force_variant);
+rbe_status rbe_plan_num_variants(const rbe_plan *plan, int32_t *n_rho, int32_t *n_force);
+rbe_status rbe_plan_get_tiles(const rbe_plan *plan, int32_t *rho_variant, int32_t *force_variant);
+
+/* Release the plan (host memory only). */
+void rbe_plan_destroy(rbe_plan *plan);
+
+/* ---------------------------------------------------------------- device calls */
+
+/*
+ * Copy the plan's metadata (system table, work lists, sampler tables) into
+ * the workspace ws (dev, rbe_plan_workspace_bytes bytes, 256-byte aligned)
+ * and wait for the copy.  Call once per workspace, before any other device
+ * call with that workspace and before any graph capture.
+ */
+rbe_status rbe_plan_upload(const rbe_plan *plan, void *ws, void *stream);
+
+/*
+ * rho(k_l) for every wave vector of every system (Sec. 2.2; Alg. 1 steps 2-3).
+ * x, y, z, q: (dev) N_total FP64 each.  m: (dev) P_total*3 int32.
+ * rho: (dev) P_total*2 FP64 (Re, Im).  ws: the uploaded workspace.
+ * In RBE_PHASE_CACHED mode this call also fills the phase cache in ws.
+ */
+rbe_status rbe_structure_factor(const rbe_plan *plan, const double *x, const double *y,
+                                const double *z, const double *q, const int32_t *m,
+                                double *rho, void *ws, void *stream);
+
+/*
+ * Forces and energies from rho (Eq. frbe with per-k weights; Alg. 1 step 4).
+ * w: (dev) P_total FP64 weights (S/P for RBE, exp(-k^2/4 alpha) for Ewald).
+ * rho: (dev) the output of rbe_structure_factor for the same inputs.
+ * F: (dev) 3*N_total values, FP64 for RBE_FP64 and FP32 for RBE_FP32_MIXED.
+ * U: (dev) B FP64 values.  In RBE_PHASE_CACHED mode the phase cache in ws
+ * must come from rbe_structure_factor on the same positions.
+ */
+rbe_status rbe_kspace_force(const rbe_plan *plan, const double *x, const double *y,
+                            const double *z, const double *q, const int32_t *m,
+                            const double *w, const double *rho, void *F, double *U, void *ws,
+                            void *stream);
+
+/*
+ * Vector-Jacobian product of (U, F) (derived from the definitions above; the
+ * paper has no adjoint).  Upstream gradients: gU (dev, B FP64) on U and gF
+ * (dev, 3*N_total, dtype of F) on F.  Outputs (dev, dtype of F): gr
+ * (3*N_total, dL/dr) and gq (N_total, dL/dq).  rho must be the forward
+ * structure factor.  Phases are recomputed (no phase cache is used).
+ */
+rbe_status rbe_kspace_vjp(const rbe_plan *plan, const double *x, const double *y,
+                          const double *z, const double *q, const int32_t *m, const double *w,
+                          const double *rho, const double *gU, const void *gF, void *gr,
+                          void *gq, void *ws, void *stream);
+
+/*
+ * Draw the wave vectors of every system on the device: system b uses the
+ * sampler of rbe_sample_k with key (seed + b, stream_id), so its rows of m
+ * equal rbe_sample_k(seed + b, stream_id, L_b, alpha_b, P_b).  m: (dev)
+ * P_total*3 int32; w: (dev) P_total FP64 receives S_b / P_b.  The plan
+ * rejects systems whose zero-vector probability exceeds 1/2.
+ */
+rbe_status rbe_sample_k_device(const rbe_plan *plan, uint64_t seed, uint64_t stream_id,
+                               int32_t *m, double *w, void *ws, void *stream);
+
+/* ---------------------------------------------------------------- diagnostics */
+
+const char *rbe_status_string(rbe_status status);
+const char *rbe_last_error(void);   /* thread-local text of the last failure on this thread */
+int32_t rbe_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBE_H */

@@ -1,0 +1,455 @@
+// Host side of the RBE library: argument checks, plans, work lists, workspace
+// layout, the host wave-vector sampler and the C entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <cstdlib>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "philox.h"
+#include "rbe.h"
+#include "rbe_internal.h"
+
+namespace rbe {
+namespace {
+
+thread_local std::string g_last_error;
+
+rbe_status fail(rbe_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+rbe_status hip_fail(hipError_t e, const char* what) {
+  return fail(RBE_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Device availability, probed once per process.
+rbe_status device_ok() {
+  static std::once_flag once;
+  static int count = 0;
+  static hipError_t err = hipSuccess;
+  std::call_once(once, [] { err = hipGetDeviceCount(&count); });
+  if (err != hipSuccess || count <= 0)
+    return fail(RBE_ENODEV, "no HIP device available (%s)", hipGetErrorString(err));
+  return RBE_OK;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// ---------------------------------------------------------------- sampler tables
+
+struct ComponentTable {
+  int32_t M = 0;
+  std::vector<double> c;   // prefix sums for j = -M..M
+};
+
+double beta_of(double L, double alpha) { return (M_PI * M_PI) / (alpha * L * L); }
+
+ComponentTable component_table(double L, double alpha) {
+  ComponentTable t;
+  const double sigma = L * std::sqrt(alpha / 2.0) / M_PI;
+  t.M = (int32_t)std::ceil(9.0 * sigma) + 1;
+  const double beta = beta_of(L, alpha);
+  t.c.resize(2 * (size_t)t.M + 1);
+  double acc = 0.0;
+  for (int32_t j = -t.M; j <= t.M; ++j) {
+    acc = acc + std::exp(-beta * (double)((int64_t)j * j));
+    t.c[(size_t)(j + t.M)] = acc;
+  }
+  return t;
+}
+
+// S = Z^3 - 1 with Z the full one-dimensional sum (window plus margin, in increasing j).
+double normalization(double L, double alpha) {
+  const ComponentTable t = component_table(L, alpha);
+  const double beta = beta_of(L, alpha);
+  double z = 0.0;
+  for (int32_t j = -t.M - 8; j <= t.M + 8; ++j) z += std::exp(-beta * (double)((int64_t)j * j));
+  return z * z * z - 1.0;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace
+}  // namespace rbe
+
+using namespace rbe;
+
+// ---------------------------------------------------------------- plan
+
+struct rbe_plan {
+  int32_t B = 0;
+  std::vector<int64_t> sys_off, k_off;
+  std::vector<double> L, alpha;
+  int precision = RBE_FP64;
+  int phase_mode = RBE_PHASE_AUTO;
+  bool cached = false;
+  int rho_variant = 0;
+  int force_variant = 1;
+  bool sampler_ok = true;
+
+  // host copies of the device tables
+  std::vector<SysDesc> sys;
+  std::vector<RhoItem> rho_items;
+  std::vector<ForceItem> force_items;
+  std::vector<int32_t> ksys;
+  std::vector<double> cdf;
+  // workspace layout (byte offsets)
+  size_t off_sys = 0, off_rho = 0, off_force = 0, off_ksys = 0, off_cdf = 0, off_part = 0,
+         off_xy = 0, off_cache = 0, total = 0;
+  int64_t n_partials = 0;   // complex slots
+  int64_t n_cache = 0;      // (cos, sin) pairs
+
+  int64_t n_total() const { return sys_off[B]; }
+  int64_t p_total() const { return k_off[B]; }
+  RhoVariant rv() const {
+    return precision == RBE_FP32_MIXED ? kRhoVariantsF32[rho_variant] : kRhoVariantsF64[rho_variant];
+  }
+};
+
+namespace {
+
+void build_layout(rbe_plan* p) {
+  const RhoVariant rv = p->rv();
+  const ForceVariant fv = kForceVariants[p->force_variant];
+  const int tile = 64 * rv.npl;
+  const int fchunk = kForceBlock * fv.nplf;
+  p->sys.assign(p->B, SysDesc{});
+  p->rho_items.clear();
+  p->force_items.clear();
+  p->ksys.assign((size_t)p->p_total(), 0);
+  int64_t part = 0, cache = 0;
+  for (int32_t b = 0; b < p->B; ++b) {
+    SysDesc& s = p->sys[b];
+    s.n_off = p->sys_off[b];
+    s.k_off = p->k_off[b];
+    s.n = (int32_t)(p->sys_off[b + 1] - p->sys_off[b]);
+    s.p = (int32_t)(p->k_off[b + 1] - p->k_off[b]);
+    s.L = p->L[b];
+    s.ntiles = (s.n + tile - 1) / tile;
+    s.part_off = part;
+    part += (int64_t)s.ntiles * s.p;
+    s.cache_off = cache;
+    if (p->cached) cache += (int64_t)s.n * s.p;
+    for (int32_t l = 0; l < s.p; ++l) p->ksys[(size_t)(s.k_off + l)] = b;
+    if (s.p > 0 && s.ntiles > 0) {
+      const int nr = (s.p + rv.krange - 1) / rv.krange;
+      int chunk = (s.p + nr - 1) / nr;
+      chunk = (chunk + rv.kc - 1) / rv.kc * rv.kc;
+      for (int32_t t = 0; t < s.ntiles; ++t)
+        for (int32_t k0 = 0; k0 < s.p; k0 += chunk)
+          p->rho_items.push_back(RhoItem{b, t, k0, std::min(chunk, s.p - k0)});
+    }
+    const int nf = std::max(1, (s.n + fchunk - 1) / fchunk);
+    for (int f = 0; f < nf; ++f) {
+      const int p0 = f * fchunk;
+      p->force_items.push_back(ForceItem{b, p0, std::max(0, std::min(fchunk, s.n - p0)), f == 0 ? 1 : 0});
+    }
+  }
+  // sampler tables: [S][c_-M .. c_M] per system
+  p->cdf.clear();
+  p->sampler_ok = true;
+  for (int32_t b = 0; b < p->B; ++b) {
+    SysDesc& s = p->sys[b];
+    const ComponentTable t = component_table(p->L[b], p->alpha[b]);
+    const double p0 = t.c[(size_t)t.M] - (t.M > 0 ? t.c[(size_t)t.M - 1] : 0.0);
+    const double pz = p0 / t.c.back();
+    if (pz * pz * pz > 0.5 || t.c.size() > (1u << 22)) {
+      p->sampler_ok = false;
+      s.cdf_len = 0;
+      s.cdf_off = (int64_t)p->cdf.size();
+      p->cdf.push_back(0.0);
+      continue;
+    }
+    s.cdf_off = (int64_t)p->cdf.size();
+    s.cdf_len = (int32_t)t.c.size();
+    p->cdf.push_back(normalization(p->L[b], p->alpha[b]));
+    p->cdf.insert(p->cdf.end(), t.c.begin(), t.c.end());
+  }
+  p->n_partials = part;
+  p->n_cache = cache;
+  size_t o = 0;
+  p->off_sys = o;   o = align_up(o + sizeof(SysDesc) * p->sys.size());
+  p->off_rho = o;   o = align_up(o + sizeof(RhoItem) * p->rho_items.size());
+  p->off_force = o; o = align_up(o + sizeof(ForceItem) * p->force_items.size());
+  p->off_ksys = o;  o = align_up(o + sizeof(int32_t) * p->ksys.size());
+  p->off_cdf = o;   o = align_up(o + sizeof(double) * p->cdf.size());
+  p->off_part = o;  o = align_up(o + 2 * sizeof(double) * (size_t)p->n_partials);
+  p->off_xy = o;    o = align_up(o + 2 * sizeof(double) * (size_t)p->p_total());
+  p->off_cache = o; o = align_up(o + 2 * sizeof(float) * (size_t)p->n_cache);
+  p->total = std::max<size_t>(o, kAlign);
+}
+
+WsView view_of(const rbe_plan* p, void* ws) {
+  char* b = static_cast<char*>(ws);
+  WsView w;
+  w.sys = reinterpret_cast<const SysDesc*>(b + p->off_sys);
+  w.rho_items = reinterpret_cast<const RhoItem*>(b + p->off_rho);
+  w.force_items = reinterpret_cast<const ForceItem*>(b + p->off_force);
+  w.ksys = reinterpret_cast<const int32_t*>(b + p->off_ksys);
+  w.cdf = reinterpret_cast<const double*>(b + p->off_cdf);
+  w.partials = reinterpret_cast<double*>(b + p->off_part);
+  w.xy = reinterpret_cast<double*>(b + p->off_xy);
+  w.cache = reinterpret_cast<float*>(b + p->off_cache);
+  return w;
+}
+
+LaunchShape shape_of(const rbe_plan* p) {
+  LaunchShape s;
+  s.B = p->B;
+  s.n_total = p->n_total();
+  s.p_total = p->p_total();
+  s.n_rho_items = (int32_t)p->rho_items.size();
+  s.n_force_items = (int32_t)p->force_items.size();
+  s.precision = p->precision;
+  s.cached = p->cached ? 1 : 0;
+  s.rv = p->rv();
+  s.rho_variant = p->rho_variant;
+  s.fv = kForceVariants[p->force_variant];
+  s.force_variant = p->force_variant;
+  return s;
+}
+
+rbe_status check_ws(const rbe_plan* p, const void* ws) {
+  if (ws == nullptr) return fail(RBE_EWORKSPACE, "workspace pointer is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign)
+    return fail(RBE_EWORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+  (void)p;
+  return RBE_OK;
+}
+
+rbe_status check_common(const rbe_plan* p, const void* ws) {
+  if (p == nullptr) return fail(RBE_EINVAL, "plan is NULL");
+  rbe_status st = check_ws(p, ws);
+  if (st != RBE_OK) return st;
+  return device_ok();
+}
+
+bool need(const void* ptr, int64_t count) { return count == 0 || ptr != nullptr; }
+
+}  // namespace
+
+// ---------------------------------------------------------------- C entry points
+
+extern "C" {
+
+int32_t rbe_abi_version(void) { return RBE_ABI_VERSION; }
+
+const char* rbe_status_string(rbe_status s) {
+  switch (s) {
+    case RBE_OK: return "RBE_OK";
+    case RBE_EINVAL: return "RBE_EINVAL: invalid argument";
+    case RBE_ENODEV: return "RBE_ENODEV: no HIP device";
+    case RBE_EHIP: return "RBE_EHIP: HIP runtime error";
+    case RBE_EWORKSPACE: return "RBE_EWORKSPACE: bad workspace";
+    case RBE_EUNSUPPORTED: return "RBE_EUNSUPPORTED: not supported";
+  }
+  return "unknown rbe_status";
+}
+
+const char* rbe_last_error(void) { return g_last_error.c_str(); }
+
+rbe_status rbe_normalization(double L, double alpha, double* S_out) {
+  if (!finite_pos(L) || !finite_pos(alpha)) return fail(RBE_EINVAL, "L and alpha must be finite and > 0");
+  if (S_out == nullptr) return fail(RBE_EINVAL, "S_out is NULL");
+  *S_out = normalization(L, alpha);
+  return RBE_OK;
+}
+
+rbe_status rbe_sample_k(uint64_t seed, uint64_t stream_id, double L, double alpha, int32_t P,
+                        int32_t* m_out, double* w_out, double* S_out) {
+  if (!finite_pos(L) || !finite_pos(alpha)) return fail(RBE_EINVAL, "L and alpha must be finite and > 0");
+  if (P < 0) return fail(RBE_EINVAL, "P must be >= 0 (got %d)", P);
+  if (P > 0 && m_out == nullptr) return fail(RBE_EINVAL, "m_out is NULL");
+  const ComponentTable t = component_table(L, alpha);
+  if (t.c.size() > (1u << 26)) return fail(RBE_EINVAL, "sampling window too large (sigma = %g)", L * std::sqrt(alpha / 2) / M_PI);
+  const double Z = t.c.back();
+  const double S = normalization(L, alpha);
+  for (int32_t l = 0; l < P; ++l) {
+    int32_t v[3] = {0, 0, 0};
+    bool ok = false;
+    for (int a = 0; a < kMaxAttempts && !ok; ++a) {
+      U64x4 ctr = {{(uint64_t)l, (uint64_t)a, 0ull, 0ull}};
+      const U64x4 r = philox4x64_10(ctr, seed, stream_id);
+      for (int d = 0; d < 3; ++d) v[d] = inverse_cdf(t.c.data(), t.M, u01_53(r.v[d]) * Z);
+      ok = v[0] != 0 || v[1] != 0 || v[2] != 0;
+    }
+    if (!ok) return fail(RBE_EINVAL, "zero wave vector drawn %d times in a row", kMaxAttempts);
+    m_out[3 * l] = v[0];
+    m_out[3 * l + 1] = v[1];
+    m_out[3 * l + 2] = v[2];
+    if (w_out) w_out[l] = S / (double)P;
+  }
+  if (S_out) *S_out = S;
+  return RBE_OK;
+}
+
+rbe_status rbe_ewald_weights(double L, double alpha, int32_t P, const int32_t* m, double* w_out) {
+  if (!finite_pos(L) || !finite_pos(alpha)) return fail(RBE_EINVAL, "L and alpha must be finite and > 0");
+  if (P < 0) return fail(RBE_EINVAL, "P must be >= 0");
+  if (P > 0 && (m == nullptr || w_out == nullptr)) return fail(RBE_EINVAL, "NULL array");
+  const double ks = 2.0 * M_PI / L;
+  for (int32_t l = 0; l < P; ++l) {
+    const double kx = ks * m[3 * l], ky = ks * m[3 * l + 1], kz = ks * m[3 * l + 2];
+    w_out[l] = std::exp(-(kx * kx + ky * ky + kz * kz) / (4.0 * alpha));
+  }
+  return RBE_OK;
+}
+
+rbe_status rbe_plan_create(int32_t B, const int64_t* sys_off, const int64_t* k_off, const double* L,
+                           const double* alpha, int32_t precision, int32_t phase_mode, rbe_plan** out) {
+  if (out == nullptr) return fail(RBE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (B <= 0) return fail(RBE_EINVAL, "B must be > 0 (got %d)", B);
+  if (!sys_off || !k_off || !L || !alpha) return fail(RBE_EINVAL, "NULL batch array");
+  if (precision != RBE_FP64 && precision != RBE_FP32_MIXED) return fail(RBE_EINVAL, "unknown precision %d", precision);
+  if (phase_mode < RBE_PHASE_AUTO || phase_mode > RBE_PHASE_CACHED) return fail(RBE_EINVAL, "unknown phase mode %d", phase_mode);
+  if (phase_mode == RBE_PHASE_CACHED && precision != RBE_FP32_MIXED)
+    return fail(RBE_EUNSUPPORTED, "the phase cache exists for RBE_FP32_MIXED only");
+  if (sys_off[0] != 0 || k_off[0] != 0) return fail(RBE_EINVAL, "offsets must start at 0");
+  for (int32_t b = 0; b < B; ++b) {
+    if (sys_off[b + 1] < sys_off[b] || k_off[b + 1] < k_off[b])
+      return fail(RBE_EINVAL, "offsets must be non-decreasing (system %d)", b);
+    if (sys_off[b + 1] - sys_off[b] > (int64_t)INT32_MAX / 2 || k_off[b + 1] - k_off[b] > (int64_t)INT32_MAX / 2)
+      return fail(RBE_EINVAL, "system %d too large", b);
+    if (!finite_pos(L[b]) || !finite_pos(alpha[b]))
+      return fail(RBE_EINVAL, "system %d: L and alpha must be finite and > 0", b);
+  }
+  rbe_plan* p = new rbe_plan();
+  p->B = B;
+  p->sys_off.assign(sys_off, sys_off + B + 1);
+  p->k_off.assign(k_off, k_off + B + 1);
+  p->L.assign(L, L + B);
+  p->alpha.assign(alpha, alpha + B);
+  p->precision = precision;
+  p->phase_mode = phase_mode;
+  // Measured: recomputing phases beats the HBM phase cache at every benchmarked shape.
+  p->cached = phase_mode == RBE_PHASE_CACHED;
+  p->rho_variant = 0;
+  p->force_variant = 1;
+  build_layout(p);
+  *out = p;
+  return RBE_OK;
+}
+
+size_t rbe_plan_workspace_bytes(const rbe_plan* p) { return p ? p->total : 0; }
+
+rbe_status rbe_plan_num_variants(const rbe_plan* p, int32_t* n_rho, int32_t* n_force) {
+  if (!p || !n_rho || !n_force) return fail(RBE_EINVAL, "NULL argument");
+  *n_rho = p->precision == RBE_FP32_MIXED ? kNumRhoVariantsF32 : kNumRhoVariantsF64;
+  *n_force = kNumForceVariants;
+  return RBE_OK;
+}
+
+rbe_status rbe_plan_get_tiles(const rbe_plan* p, int32_t* rv, int32_t* fv) {
+  if (!p || !rv || !fv) return fail(RBE_EINVAL, "NULL argument");
+  *rv = p->rho_variant;
+  *fv = p->force_variant;
+  return RBE_OK;
+}
+
+rbe_status rbe_plan_set_tiles(rbe_plan* p, int32_t rv, int32_t fv) {
+  if (!p) return fail(RBE_EINVAL, "plan is NULL");
+  const int nr = p->precision == RBE_FP32_MIXED ? kNumRhoVariantsF32 : kNumRhoVariantsF64;
+  if (rv < -1 || rv >= nr) return fail(RBE_EINVAL, "rho variant %d out of range [0, %d)", rv, nr);
+  if (fv < -1 || fv >= kNumForceVariants) return fail(RBE_EINVAL, "force variant %d out of range", fv);
+  if (rv >= 0) p->rho_variant = rv;
+  if (fv >= 0) p->force_variant = fv;
+  build_layout(p);
+  return RBE_OK;
+}
+
+void rbe_plan_destroy(rbe_plan* p) { delete p; }
+
+rbe_status rbe_plan_upload(const rbe_plan* p, void* ws, void* stream) {
+  rbe_status st = check_common(p, ws);
+  if (st != RBE_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* b = static_cast<char*>(ws);
+  struct Copy { size_t off; const void* src; size_t bytes; } copies[] = {
+      {p->off_sys, p->sys.data(), sizeof(SysDesc) * p->sys.size()},
+      {p->off_rho, p->rho_items.data(), sizeof(RhoItem) * p->rho_items.size()},
+      {p->off_force, p->force_items.data(), sizeof(ForceItem) * p->force_items.size()},
+      {p->off_ksys, p->ksys.data(), sizeof(int32_t) * p->ksys.size()},
+      {p->off_cdf, p->cdf.data(), sizeof(double) * p->cdf.size()},
+  };
+  for (const Copy& c : copies) {
+    if (c.bytes == 0) continue;
+    hipError_t e = hipMemcpyAsync(b + c.off, c.src, c.bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(plan upload)");
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(plan upload)");
+  return RBE_OK;
+}
+
+rbe_status rbe_structure_factor(const rbe_plan* p, const double* x, const double* y, const double* z,
+                                const double* q, const int32_t* m, double* rho, void* ws, void* stream) {
+  rbe_status st = check_common(p, ws);
+  if (st != RBE_OK) return st;
+  const int64_t n = p->n_total(), P = p->p_total();
+  if (!need(x, n) || !need(y, n) || !need(z, n) || !need(q, n)) return fail(RBE_EINVAL, "NULL position/charge array");
+  if (!need(m, P) || !need(rho, P)) return fail(RBE_EINVAL, "NULL m or rho array");
+  hipError_t e = launch_rho(shape_of(p), view_of(p, ws), x, y, z, q, m, rho, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "rho pass launch");
+  return RBE_OK;
+}
+
+rbe_status rbe_kspace_force(const rbe_plan* p, const double* x, const double* y, const double* z,
+                            const double* q, const int32_t* m, const double* w, const double* rho,
+                            void* F, double* U, void* ws, void* stream) {
+  rbe_status st = check_common(p, ws);
+  if (st != RBE_OK) return st;
+  const int64_t n = p->n_total(), P = p->p_total();
+  if (!need(x, n) || !need(y, n) || !need(z, n) || !need(q, n) || !need(F, n))
+    return fail(RBE_EINVAL, "NULL position/charge/force array");
+  if (!need(m, P) || !need(w, P) || !need(rho, P)) return fail(RBE_EINVAL, "NULL m, w or rho array");
+  if (U == nullptr) return fail(RBE_EINVAL, "U is NULL");
+  hipError_t e = launch_force(shape_of(p), view_of(p, ws), x, y, z, q, m, w, rho, F, U,
+                              static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "force pass launch");
+  return RBE_OK;
+}
+
+rbe_status rbe_kspace_vjp(const rbe_plan* p, const double* x, const double* y, const double* z,
+                          const double* q, const int32_t* m, const double* w, const double* rho,
+                          const double* gU, const void* gF, void* gr, void* gq, void* ws, void* stream) {
+  rbe_status st = check_common(p, ws);
+  if (st != RBE_OK) return st;
+  const int64_t n = p->n_total(), P = p->p_total();
+  if (!need(x, n) || !need(y, n) || !need(z, n) || !need(q, n) || !need(gF, n) || !need(gr, n) || !need(gq, n))
+    return fail(RBE_EINVAL, "NULL particle array");
+  if (!need(m, P) || !need(w, P) || !need(rho, P)) return fail(RBE_EINVAL, "NULL m, w or rho array");
+  if (gU == nullptr) return fail(RBE_EINVAL, "gU is NULL");
+  hipError_t e = launch_vjp(shape_of(p), view_of(p, ws), x, y, z, q, m, w, rho, gU, gF, gr, gq,
+                            static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "vjp launch");
+  return RBE_OK;
+}
+
+rbe_status rbe_sample_k_device(const rbe_plan* p, uint64_t seed, uint64_t stream_id, int32_t* m, double* w,
+                               void* ws, void* stream) {
+  rbe_status st = check_common(p, ws);
+  if (st != RBE_OK) return st;
+  if (!p->sampler_ok) return fail(RBE_EINVAL, "a system's zero-vector probability exceeds 1/2 (box too small for alpha)");
+  const int64_t P = p->p_total();
+  if (!need(m, P) || !need(w, P)) return fail(RBE_EINVAL, "NULL m or w array");
+  hipError_t e = launch_sample(shape_of(p), view_of(p, ws), seed, stream_id, m, w, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "sampler launch");
+  return RBE_OK;
+}
+
+}  // extern "C"

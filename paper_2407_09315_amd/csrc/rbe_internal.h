@@ -1,0 +1,98 @@
+// Internal types shared by the host plan code and the gfx950 kernels.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <hip/hip_runtime.h>
+
+#include "rbe.h"
+
+namespace rbe {
+
+// Per-system metadata, one 64-byte row per system in the workspace.
+struct SysDesc {
+  int64_t n_off;      // first particle of the system in the concatenated arrays
+  int64_t k_off;      // first wave vector
+  int64_t part_off;   // first partial-sum slot (complex) of the system's [p][ntiles] block
+  int64_t cache_off;  // first (cos, sin) slot of the system's [p][n] phase cache
+  int32_t n;          // particles
+  int32_t p;          // wave vectors
+  int32_t ntiles;     // rho-pass particle tiles
+  int32_t cdf_len;    // 2M+1 entries of the sampler's prefix-sum table (0: no table)
+  double L;
+  int64_t cdf_off;    // first entry of the sampler table (doubles)
+};
+static_assert(sizeof(SysDesc) == 64, "SysDesc layout");
+
+// rho-pass work item: one particle tile x one range of wave vectors.
+struct RhoItem {
+  int32_t sys;
+  int32_t tile;
+  int32_t k0;   // first local wave vector
+  int32_t nk;   // number of wave vectors
+};
+
+// force-pass work item: a contiguous particle range of one system.
+struct ForceItem {
+  int32_t sys;
+  int32_t p0;     // first local particle
+  int32_t np;     // particles
+  int32_t flags;  // bit 0: this block writes the system's energy
+};
+
+// Kernel variant tables (the autotuner picks one entry of each).
+struct RhoVariant { int npl; int kc; int krange; };   // particles per lane, k per chunk, k per item
+struct ForceVariant { int nplf; };                       // particles per lane (256-thread blocks)
+
+constexpr int kNumRhoVariantsF32 = 4;
+constexpr int kNumRhoVariantsF64 = 3;
+constexpr int kNumForceVariants = 3;
+extern const RhoVariant kRhoVariantsF32[kNumRhoVariantsF32];
+extern const RhoVariant kRhoVariantsF64[kNumRhoVariantsF64];
+extern const ForceVariant kForceVariants[kNumForceVariants];
+
+constexpr int kForceBlock = 256;
+constexpr int kReduceBlock = 256;
+constexpr int kMaxAttempts = 1024;
+
+// Device-side views of the workspace regions.
+struct WsView {
+  const SysDesc* sys;
+  const RhoItem* rho_items;
+  const ForceItem* force_items;
+  const int32_t* ksys;   // system of each wave vector
+  const double* cdf;     // sampler tables
+  double* partials;      // complex partial sums (rho pass, then VJP pass B1)
+  double* xy;            // P_total complex values (VJP X + iY)
+  float* cache;          // (cos, sin) phase cache, FP32_MIXED + CACHED only
+};
+
+struct LaunchShape {
+  int32_t B;
+  int64_t n_total;
+  int64_t p_total;
+  int32_t n_rho_items;
+  int32_t n_force_items;
+  int precision;
+  int cached;
+  RhoVariant rv;
+  int rho_variant;
+  ForceVariant fv;
+  int force_variant;
+};
+
+// Kernel launchers (rbe_kernels.hip).  Each returns hipSuccess or the launch error.
+hipError_t launch_rho(const LaunchShape& s, const WsView& w, const double* x, const double* y,
+                      const double* z, const double* q, const int32_t* m, double* rho,
+                      hipStream_t st);
+hipError_t launch_force(const LaunchShape& s, const WsView& w, const double* x, const double* y,
+                        const double* z, const double* q, const int32_t* m, const double* wk,
+                        const double* rho, void* F, double* U, hipStream_t st);
+hipError_t launch_vjp(const LaunchShape& s, const WsView& w, const double* x, const double* y,
+                      const double* z, const double* q, const int32_t* m, const double* wk,
+                      const double* rho, const double* gU, const void* gF, void* gr, void* gq,
+                      hipStream_t st);
+hipError_t launch_sample(const LaunchShape& s, const WsView& w, uint64_t seed, uint64_t stream_id,
+                         int32_t* m, double* wk, hipStream_t st);
+
+}  // namespace rbe

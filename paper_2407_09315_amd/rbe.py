@@ -1,0 +1,237 @@
+"""Python binding of the RBE C ABI (argument marshalling only).
+
+Functions with the C names take torch tensors (device memory) or numpy arrays
+(host memory) and pass raw pointers; every computation happens in librbe.so.
+``Plan`` bundles a plan, its device workspace and the current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (RBE_FP32_MIXED, RBE_FP64, RBE_PHASE_AUTO, RBE_PHASE_CACHED,  # noqa: F401
+                   RBE_PHASE_RECOMPUTE, RBEError, check, load)
+
+PRECISIONS = {"fp64": RBE_FP64, "fp32_mixed": RBE_FP32_MIXED}
+PHASE_MODES = {"auto": RBE_PHASE_AUTO, "recompute": RBE_PHASE_RECOMPUTE, "cached": RBE_PHASE_CACHED}
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    if t is None:
+        return ctypes.c_void_p(0)
+    if isinstance(t, torch.Tensor):
+        return ctypes.c_void_p(t.data_ptr())
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data_as(ctypes.c_void_p)
+    if isinstance(t, int):
+        return ctypes.c_void_p(t)
+    raise TypeError(f"cannot pass {type(t)} as a pointer")
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor (got {t.dtype})")
+    return t
+
+
+# ---------------------------------------------------------------------- host calls
+
+def rbe_sample_k(seed: int, stream_id: int, L: float, alpha: float, P: int):
+    """(m (P, 3) int32, w (P,) float64 = S/P, S) from the library's host sampler."""
+    m = np.zeros((P, 3), dtype=np.int32)
+    w = np.zeros(P, dtype=np.float64)
+    S = np.zeros(1, dtype=np.float64)
+    check(load().rbe_sample_k(seed, stream_id, L, alpha, P, _ptr(m), _ptr(w), _ptr(S)), "rbe_sample_k")
+    return m, w, float(S[0])
+
+
+def rbe_normalization(L: float, alpha: float) -> float:
+    S = np.zeros(1, dtype=np.float64)
+    check(load().rbe_normalization(L, alpha, _ptr(S)), "rbe_normalization")
+    return float(S[0])
+
+
+def rbe_ewald_weights(L: float, alpha: float, m: np.ndarray) -> np.ndarray:
+    m = np.ascontiguousarray(m, dtype=np.int32)
+    w = np.zeros(m.shape[0], dtype=np.float64)
+    check(load().rbe_ewald_weights(L, alpha, m.shape[0], _ptr(m), _ptr(w)), "rbe_ewald_weights")
+    return w
+
+
+# ---------------------------------------------------------------------- device calls (C names)
+
+def rbe_plan_upload(plan, ws, stream=None):
+    check(load().rbe_plan_upload(plan, _ptr(ws), _stream(stream)), "rbe_plan_upload")
+
+
+def rbe_structure_factor(plan, x, y, z, q, m, rho, ws, stream=None):
+    check(load().rbe_structure_factor(plan, _ptr(x), _ptr(y), _ptr(z), _ptr(q), _ptr(m), _ptr(rho),
+                                      _ptr(ws), _stream(stream)), "rbe_structure_factor")
+
+
+def rbe_kspace_force(plan, x, y, z, q, m, w, rho, F, U, ws, stream=None):
+    check(load().rbe_kspace_force(plan, _ptr(x), _ptr(y), _ptr(z), _ptr(q), _ptr(m), _ptr(w), _ptr(rho),
+                                  _ptr(F), _ptr(U), _ptr(ws), _stream(stream)), "rbe_kspace_force")
+
+
+def rbe_kspace_vjp(plan, x, y, z, q, m, w, rho, gU, gF, gr, gq, ws, stream=None):
+    check(load().rbe_kspace_vjp(plan, _ptr(x), _ptr(y), _ptr(z), _ptr(q), _ptr(m), _ptr(w), _ptr(rho),
+                                _ptr(gU), _ptr(gF), _ptr(gr), _ptr(gq), _ptr(ws), _stream(stream)),
+          "rbe_kspace_vjp")
+
+
+def rbe_sample_k_device(plan, seed, stream_id, m, w, ws, stream=None):
+    check(load().rbe_sample_k_device(plan, seed, stream_id, _ptr(m), _ptr(w), _ptr(ws), _stream(stream)),
+          "rbe_sample_k_device")
+
+
+# ---------------------------------------------------------------------- plan object
+
+@dataclass
+class Batch:
+    sys_off: np.ndarray   # (B+1,) int64
+    k_off: np.ndarray     # (B+1,) int64
+    L: np.ndarray         # (B,) float64
+    alpha: np.ndarray     # (B,) float64
+
+    @staticmethod
+    def single(n: int, p: int, L: float, alpha: float) -> "Batch":
+        return Batch(np.array([0, n], dtype=np.int64), np.array([0, p], dtype=np.int64),
+                     np.array([L], dtype=np.float64), np.array([alpha], dtype=np.float64))
+
+    @staticmethod
+    def from_sizes(ns, ps, Ls, alphas) -> "Batch":
+        so = np.concatenate([[0], np.cumsum(np.asarray(ns, dtype=np.int64))]).astype(np.int64)
+        ko = np.concatenate([[0], np.cumsum(np.asarray(ps, dtype=np.int64))]).astype(np.int64)
+        return Batch(so, ko, np.asarray(Ls, dtype=np.float64), np.asarray(alphas, dtype=np.float64))
+
+    @property
+    def B(self) -> int:
+        return int(self.L.shape[0])
+
+
+class Plan:
+    """A plan for a batch of systems plus its device workspace (a torch uint8 tensor)."""
+
+    def __init__(self, batch: Batch, precision: str = "fp32_mixed", phase_mode: str = "auto",
+                 device=None, tiles=None):
+        self.lib = load()
+        self.batch = batch
+        self.precision = precision
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.n_total = int(batch.sys_off[-1])
+        self.p_total = int(batch.k_off[-1])
+        self._arrays = [np.ascontiguousarray(a) for a in (batch.sys_off, batch.k_off, batch.L, batch.alpha)]
+        handle = ctypes.c_void_p()
+        check(self.lib.rbe_plan_create(batch.B, *[_ptr(a) for a in self._arrays], PRECISIONS[precision],
+                                       PHASE_MODES[phase_mode], ctypes.byref(handle)), "rbe_plan_create")
+        self.handle = handle
+        if tiles is not None:
+            check(self.lib.rbe_plan_set_tiles(self.handle, int(tiles[0]), int(tiles[1])), "rbe_plan_set_tiles")
+        self._alloc()
+
+    def _alloc(self):
+        nbytes = int(self.lib.rbe_plan_workspace_bytes(self.handle))
+        # over-allocate by 256 bytes and slice to a 256-byte boundary
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._raw = raw
+        self.ws = raw[off:off + nbytes]
+        rbe_plan_upload(self.handle, self.ws)
+
+    def set_tiles(self, rho_variant: int, force_variant: int):
+        check(self.lib.rbe_plan_set_tiles(self.handle, rho_variant, force_variant), "rbe_plan_set_tiles")
+        self._alloc()
+
+    def tiles(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        check(self.lib.rbe_plan_get_tiles(self.handle, ctypes.byref(a), ctypes.byref(b)), "rbe_plan_get_tiles")
+        return a.value, b.value
+
+    def num_variants(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        check(self.lib.rbe_plan_num_variants(self.handle, ctypes.byref(a), ctypes.byref(b)), "rbe_plan_num_variants")
+        return a.value, b.value
+
+    @property
+    def force_dtype(self):
+        return torch.float32 if self.precision == "fp32_mixed" else torch.float64
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.rbe_plan_destroy(h)
+            self.handle = None
+
+    # -- device calls (inputs: float64 x, y, z, q; int32 m (P_total, 3); float64 w)
+    def _check_particles(self, x, y, z, q):
+        for name, t in (("x", x), ("y", y), ("z", z), ("q", q)):
+            _dev(t, torch.float64, name)
+            if t.numel() != self.n_total:
+                raise ValueError(f"{name} has {t.numel()} elements, plan expects {self.n_total}")
+
+    def _check_k(self, m, w=None):
+        _dev(m, torch.int32, "m")
+        if m.numel() != 3 * self.p_total:
+            raise ValueError(f"m has {m.numel()} elements, plan expects {3 * self.p_total}")
+        if w is not None:
+            _dev(w, torch.float64, "w")
+            if w.numel() != self.p_total:
+                raise ValueError(f"w has {w.numel()} elements, plan expects {self.p_total}")
+
+    def structure_factor(self, x, y, z, q, m, rho=None, stream=None):
+        self._check_particles(x, y, z, q)
+        self._check_k(m)
+        if rho is None:
+            rho = torch.empty((self.p_total, 2), dtype=torch.float64, device=self.device)
+        rbe_structure_factor(self.handle, x, y, z, q, m, rho, self.ws, stream)
+        return rho
+
+    def kspace_force(self, x, y, z, q, m, w, rho, F=None, U=None, stream=None):
+        self._check_particles(x, y, z, q)
+        self._check_k(m, w)
+        if F is None:
+            F = torch.empty((3, self.n_total), dtype=self.force_dtype, device=self.device)
+        if U is None:
+            U = torch.empty(self.batch.B, dtype=torch.float64, device=self.device)
+        rbe_kspace_force(self.handle, x, y, z, q, m, w, rho, F, U, self.ws, stream)
+        return F, U
+
+    def forward(self, x, y, z, q, m, w, stream=None):
+        rho = self.structure_factor(x, y, z, q, m, stream=stream)
+        F, U = self.kspace_force(x, y, z, q, m, w, rho, stream=stream)
+        return F, U, rho
+
+    def kspace_vjp(self, x, y, z, q, m, w, rho, gU, gF, gr=None, gq=None, stream=None):
+        self._check_particles(x, y, z, q)
+        self._check_k(m, w)
+        _dev(gU, torch.float64, "gU")
+        _dev(gF, self.force_dtype, "gF")
+        if gr is None:
+            gr = torch.empty((3, self.n_total), dtype=self.force_dtype, device=self.device)
+        if gq is None:
+            gq = torch.empty(self.n_total, dtype=self.force_dtype, device=self.device)
+        rbe_kspace_vjp(self.handle, x, y, z, q, m, w, rho, gU, gF, gr, gq, self.ws, stream)
+        return gr, gq
+
+    def sample_k_device(self, seed: int, stream_id: int, m=None, w=None, stream=None):
+        if m is None:
+            m = torch.empty((self.p_total, 3), dtype=torch.int32, device=self.device)
+        if w is None:
+            w = torch.empty(self.p_total, dtype=torch.float64, device=self.device)
+        rbe_sample_k_device(self.handle, seed, stream_id, m, w, self.ws, stream)
+        return m, w

@@ -1,0 +1,192 @@
+"""GPU checks of the adjoint, the on-device sampler and the batched form.
+
+  * VJP (FP64) against the oracle's VJP and central finite differences of the
+    GPU FP64 forward (h = 1e-5 A) on 64 coordinates and 64 charges of the
+    200k-charge box, loss L = sum |F - F_ref|^2 + U;
+  * VJP (FP32-mixed) against the FP64 oracle VJP at the FP32 tolerance;
+  * torch.autograd through RBEKSpace matches the same gradients;
+  * the device sampler equals the host sampler and the oracle sampler bit for bit;
+  * a batch of uneven systems equals per-system single-batch calls, bitwise;
+  * the mean of many RBE batches converges to the full Ewald force (unbiasedness).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import rbe_inputs as ri
+from oracle import sampler
+from paper_2407_09315_amd import Batch, Plan, rbe_kspace, rbe_sample_k
+from parity_util import FP32_TOL, dev, force_err, note, particles, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _vjp_case(s, alpha, P, precision, seed=2005):
+    m, w, _ = rbe_sample_k(seed, 0, s.L, alpha, P)
+    plan = Plan(Batch.single(s.n, P, s.L, alpha), precision=precision, device=dev())
+    X = particles(s)
+    mt, wt = to_dev(m, torch.int32), to_dev(w)
+    F, U, rho = plan.forward(*X, mt, wt)
+    Fref = ri.gaussian_vectors(s.n, 3005)
+    gF = (2.0 * (F.double() - to_dev(Fref))).to(plan.force_dtype).contiguous()
+    gU = torch.ones(1, dtype=torch.float64, device=dev())
+    gr, gq = plan.kspace_vjp(*X, mt, wt, rho, gU, gF)
+    torch.cuda.synchronize()
+    return plan, m, w, X, mt, wt, Fref, F, gF, gr.double().cpu().numpy(), gq.double().cpu().numpy()
+
+
+def _grad_err(g, g_ref):
+    return float(np.sqrt(np.sum((g - g_ref) ** 2) / np.sum(g_ref ** 2)))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_vjp_vs_oracle_small(precision):
+    s, alpha, P = ri.c1_small()
+    note(f"case vjp c1 {precision}")
+    plan, m, w, X, mt, wt, Fref, F, gF, gr, gq = _vjp_case(s, alpha, P, precision)
+    gr_ref, gq_ref = oracle.vjp(s.x, s.y, s.z, s.q, m, w, s.L, 1.0, gF.double().cpu().numpy())
+    er, eq = _grad_err(gr, gr_ref), _grad_err(gq, gq_ref)
+    note(f"  dL/dr {er:.2e}  dL/dq {eq:.2e}")
+    tol = 1e-12 if precision == "fp64" else FP32_TOL
+    assert er < tol and eq < tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_vjp_vs_oracle_c4(precision):
+    s, alpha, P = ri.c4_differentiable()
+    note(f"case vjp c4 {precision}")
+    plan, m, w, X, mt, wt, Fref, F, gF, gr, gq = _vjp_case(s, alpha, P, precision)
+    gr_ref, gq_ref = oracle.vjp(s.x, s.y, s.z, s.q, m, w, s.L, 1.0, gF.double().cpu().numpy())
+    er, eq = _grad_err(gr, gr_ref), _grad_err(gq, gq_ref)
+    note(f"  dL/dr {er:.2e}  dL/dq {eq:.2e}")
+    tol = 1e-11 if precision == "fp64" else FP32_TOL
+    assert er < tol and eq < tol
+
+
+def test_vjp_finite_differences_c4():
+    """Central differences of the GPU FP64 loss on 64 coordinates and 64 charges."""
+    s, alpha, P = ri.c4_differentiable()
+    plan, m, w, X, mt, wt, Fref, F, gF, gr, gq = _vjp_case(s, alpha, P, "fp64")
+    Fref_t = to_dev(Fref)
+
+    def loss(Xp):
+        Fp, Up, _ = plan.forward(*Xp, mt, wt)
+        d = Fp - Fref_t
+        return float(torch.sum(d * d).item() + Up.sum().item())
+
+    g = np.random.default_rng(4005)
+    h = 1e-5
+    rows = []
+    for i, d in zip(g.choice(s.n, 64, replace=False), g.integers(0, 3, 64)):
+        Xp = [t.clone() for t in X]
+        Xm = [t.clone() for t in X]
+        Xp[d][i] += h
+        Xm[d][i] -= h
+        rows.append(((loss(Xp) - loss(Xm)) / (2 * h), gr[d, i]))
+    for i in g.choice(s.n, 64, replace=False):
+        Xp = [t.clone() for t in X]
+        Xm = [t.clone() for t in X]
+        Xp[3][i] += h
+        Xm[3][i] -= h
+        rows.append(((loss(Xp) - loss(Xm)) / (2 * h), gq[i]))
+    fd = np.array([r[0] for r in rows])
+    an = np.array([r[1] for r in rows])
+    scale = max(np.sqrt(np.mean(an ** 2)), 1e-30)
+    err = np.abs(fd - an) / np.maximum(np.abs(fd), scale)
+    note(f"  FD max rel err {err.max():.2e} (median {np.median(err):.2e})")
+    assert err.max() < 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_autograd_function(precision):
+    s, alpha, P = ri.e3_electrolyte()
+    m, w, _ = rbe_sample_k(9, 0, s.L, alpha, P)
+    plan = Plan(Batch.single(s.n, P, s.L, alpha), precision=precision, device=dev())
+    X = [t.requires_grad_(True) for t in particles(s)]
+    U, F = rbe_kspace(*X, to_dev(m, torch.int32), to_dev(w), plan)
+    (U.sum() + (F.double() ** 2).sum()).backward()
+    F_ref, _, _ = oracle.force_energy(s.x, s.y, s.z, s.q, m, w, s.L)
+    gr_ref, gq_ref = oracle.vjp(s.x, s.y, s.z, s.q, m, w, s.L, 1.0, 2 * F.detach().double().cpu().numpy())
+    tol = 1e-12 if precision == "fp64" else FP32_TOL
+    for d in range(3):
+        assert _grad_err(X[d].grad.cpu().numpy(), gr_ref[d]) < tol
+    assert _grad_err(X[3].grad.cpu().numpy(), gq_ref) < tol
+    if precision == "fp64":
+        assert torch.autograd.gradcheck(
+            lambda a: rbe_kspace(a, X[1].detach(), X[2].detach(), X[3].detach(), to_dev(m[:5], torch.int32),
+                                 to_dev(w[:5]), Plan(Batch.single(s.n, 5, s.L, alpha), "fp64", device=dev()))[0],
+            (X[0].detach().clone().requires_grad_(True),), eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+def test_device_sampler_bit_exact():
+    reps = ri.c5_replicas(B=12)
+    ns = [s.n for s in reps.systems]
+    Ls = [s.L for s in reps.systems] + [2.0]
+    alphas = reps.alphas + [1.5]
+    ps = [100] * 12 + [50]
+    plan = Plan(Batch.from_sizes(ns + [4], ps, Ls, alphas), precision="fp32_mixed", device=dev())
+    m, w = plan.sample_k_device(6000, 3)
+    torch.cuda.synchronize()
+    m, w = m.cpu().numpy(), w.cpu().numpy()
+    off = 0
+    for b, P in enumerate(ps):
+        mh, wh, S = rbe_sample_k(6000 + b, 3, Ls[b], alphas[b], P)
+        mo, So = sampler.sample_k(6000 + b, 3, Ls[b], alphas[b], P)
+        assert np.array_equal(m[off:off + P], mh) and np.array_equal(mh, mo)
+        assert np.array_equal(w[off:off + P], wh)
+        off += P
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_batched_equals_single(precision):
+    reps = ri.c5_replicas(B=10)
+    systems = reps.systems + [ri.random_charges(3, 4.0, 1), ri.uniform_pm1(2000, 20.0, 2)]
+    alphas = reps.alphas + [0.7, 0.2]
+    ps = [100] * 10 + [5, 0]
+    batch = Batch.from_sizes([s.n for s in systems], ps, [s.L for s in systems], alphas)
+    plan = Plan(batch, precision=precision, device=dev())
+    m, w = plan.sample_k_device(6000, 0)
+    cat = [to_dev(np.concatenate([getattr(s, a) for s in systems])) for a in ("x", "y", "z", "q")]
+    F, U, rho = plan.forward(*cat, m, w)
+    torch.cuda.synchronize()
+    F, U, rho = F.cpu().numpy(), U.cpu().numpy(), rho.cpu().numpy()
+    mh, wh = m.cpu().numpy(), w.cpu().numpy()
+    no = ko = 0
+    for b, s in enumerate(systems):
+        P = ps[b]
+        sp = Plan(Batch.single(s.n, P, s.L, alphas[b]), precision=precision, device=dev())
+        Fs, Us, rs = sp.forward(*particles(s), to_dev(mh[ko:ko + P], torch.int32), to_dev(wh[ko:ko + P]))
+        torch.cuda.synchronize()
+        assert np.array_equal(Fs.cpu().numpy(), F[:, no:no + s.n]), b
+        assert Us.cpu().numpy()[0] == U[b] and np.array_equal(rs.cpu().numpy(), rho[ko:ko + P])
+        no += s.n
+        ko += P
+    # and against the oracle for one replica
+    s0 = systems[0]
+    F_ref, U_ref, _ = oracle.force_energy(s0.x, s0.y, s0.z, s0.q, mh[:100], wh[:100], s0.L)
+    tol = 1e-12 if precision == "fp64" else FP32_TOL
+    assert force_err(F[:, :s0.n], F_ref) < tol and rel(U[0], U_ref) < tol
+
+
+def test_unbiased_against_full_ewald():
+    """Mean of B = 2000 RBE batches (device sampler) vs the full Ewald k-space force (z-test)."""
+    s, alpha, P = ri.c1_small()
+    B = 2000
+    mref = sampler.all_vectors(10)
+    wref = sampler.ewald_weights(mref, s.L, alpha)
+    Fe, Ue, _ = oracle.force_energy(s.x, s.y, s.z, s.q, mref, wref, s.L)
+    plan = Plan(Batch.from_sizes([s.n] * B, [P] * B, [s.L] * B, [alpha] * B), precision="fp64", device=dev())
+    m, w = plan.sample_k_device(2001, 0)
+    cat = [t.repeat(B) for t in particles(s)]
+    F, U, _ = plan.forward(*cat, m, w)
+    F = F.cpu().numpy().reshape(3, B, s.n)
+    U = U.cpu().numpy()
+    mean, sd = F.mean(axis=1), F.std(axis=1, ddof=1) / math.sqrt(B)
+    z = (mean - Fe) / sd
+    rms = math.sqrt(np.mean(z * z))
+    zU = (U.mean() - Ue) / (U.std(ddof=1) / math.sqrt(B))
+    note(f"  RMS z {rms:.3f}, max |z| {np.abs(z).max():.2f}, z_U {zU:.2f}")
+    assert 0.9 < rms < 1.1 and np.abs(z).max() < 6 and abs(zU) < 4
