@@ -52,66 +52,47 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-class Timer:
-    """HIP events on torch's current stream (the stream every library call is enqueued on)."""
-
-    def __init__(self, torch):
-        self.torch = torch
-        self.events = []
-
-    def mark(self):
-        e = self.torch.cuda.Event(enable_timing=True)
-        e.record()
-        self.events.append(e)
-        return e
-
-
 def run_form(torch, plan_cls, batch_cls, X, L, alpha, P, precision, phase_mode, steps, warmup, seed=2003):
-    from paper_2407_09315_amd import Batch, Plan  # noqa: F401
+    """Time whole evaluations replayed from one captured HIP graph, then time the two
+    passes' kernels with HIP events placed around them on the launch stream."""
     n = X[0].numel()
+    dev = X[0].device
     plan = plan_cls(batch_cls.single(n, P, L, alpha), precision=precision, phase_mode=phase_mode)
-    m, w = plan.sample_k_device(seed, 0)
-    rho = torch.empty((P, 2), dtype=torch.float64, device=X[0].device)
-    F = torch.empty((3, n), dtype=plan.force_dtype, device=X[0].device)
-    U = torch.empty(1, dtype=torch.float64, device=X[0].device)
-
-    def step(k, ev=None):
-        plan.sample_k_device(seed, k, m, w)
-        if ev is not None:
-            ev.append(torch.cuda.Event(enable_timing=True))
-            ev[-1].record()
-        plan.structure_factor(*X, m, rho)
-        if ev is not None:
-            ev.append(torch.cuda.Event(enable_timing=True))
-            ev[-1].record()
-        plan.kspace_force(*X, m, w, rho, F, U)
-        if ev is not None:
-            ev.append(torch.cuda.Event(enable_timing=True))
-            ev[-1].record()
-
-    for k in range(warmup):
-        step(k)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(steps):
-        step(warmup + k)
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / steps
-    # per-kernel durations, measured in a second pass so the events do not perturb the wall time
-    ev = []
-    for k in range(steps):
-        step(warmup + k, ev)
-    torch.cuda.synchronize()
-    t_rho = np.mean([ev[3 * i].elapsed_time(ev[3 * i + 1]) for i in range(steps)]) * 1e-3
-    t_force = np.mean([ev[3 * i + 1].elapsed_time(ev[3 * i + 2]) for i in range(steps)]) * 1e-3
-    # the result of the first timed step's wave vectors, for the error statement
-    plan.sample_k_device(seed, warmup, m, w)
-    plan.structure_factor(*X, m, rho)
-    plan.kspace_force(*X, m, w, rho, F, U)
-    torch.cuda.synchronize()
-    return {"wall_s": wall, "t_rho_s": float(t_rho), "t_force_s": float(t_force),
-            "m": m.cpu().numpy(), "w": w.cpu().numpy(), "F": F.double().cpu().numpy(),
-            "U": float(U.cpu()[0]), "rho": rho.cpu().numpy()}
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        counter = torch.zeros(1, dtype=torch.int64, device=dev)
+        g = plan.graph(*X, seed=seed, stream_base=0, step_counter=counter)
+        for _ in range(warmup):
+            g.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.launch()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        out = {"wall_s": wall, "m": g.m.cpu().numpy(), "w": g.w.cpu().numpy(), "F": g.F.double().cpu().numpy(),
+               "U": float(g.U.cpu()[0]), "rho": g.rho.cpu().numpy(), "tiles": plan.tiles()}
+        # kernel timing: the same step as eager calls, events around each pass's kernel
+        m = torch.empty_like(g.m)
+        w = torch.empty_like(g.w)
+        rho = torch.empty_like(g.rho)
+        F = torch.empty_like(g.F)
+        U = torch.empty_like(g.U)
+        evs = []
+        for k in range(steps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            for e in ev:
+                e.record()
+            plan.set_timing_events(*ev)
+            plan.sample_k_device(seed, k, m, w)
+            plan.structure_factor(*X, m, rho)
+            plan.kspace_force(*X, m, w, rho, F, U)
+            evs.append(ev)
+        plan.set_timing_events()
+        torch.cuda.synchronize()
+    out["t_rho_s"] = float(np.mean([e[0].elapsed_time(e[1]) for e in evs])) * 1e-3
+    out["t_force_s"] = float(np.mean([e[2].elapsed_time(e[3]) for e in evs])) * 1e-3
+    return out
 
 
 def main():
@@ -142,7 +123,7 @@ def main():
     if not args.quick:
         r = run_form(torch, Plan, Batch, X, s.L, alpha, P, "fp32_mixed", "cached", max(5, args.steps // 5), 3)
         extra["fp32_mixed_cached_phase_P100"] = {"ms_per_step": r["wall_s"] * 1e3, "G_terms_per_s": terms / r["wall_s"] / 1e9,
-                                                 "rho_call_ms": r["t_rho_s"] * 1e3, "force_call_ms": r["t_force_s"] * 1e3}
+                                                 "rho_kernel_ms": r["t_rho_s"] * 1e3, "force_kernel_ms": r["t_force_s"] * 1e3}
         log("cached done")
         for prec, key in (("fp32_mixed", "fp32_mixed_P200"), ("fp64", "fp64_P200")):
             r = run_form(torch, Plan, Batch, X, s.L, alpha, 200, prec, "recompute", max(5, args.steps // 5), 3)
@@ -175,12 +156,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": "water+1M NaCl electrolyte, N=1,000,000, L=217.0535 A, alpha=0.06, P=100",
                    "N": s.n, "P": P, "L": s.L, "alpha": alpha, "precision": "fp32_mixed",
-                   "phase_mode": "recompute", "step": "device sampling + rho pass + reduction + force pass"},
+                   "phase_mode": "recompute",
+                   "step": "device sampling + rho pass + reduction + force pass, replayed as one HIP graph"},
         "fp64": {"ms_per_step": round(f64["wall_s"] * 1e3, 4), "G_terms_per_s": round(terms / f64["wall_s"] / 1e9, 3),
-                 "rho_call_ms": round(f64["t_rho_s"] * 1e3, 4), "force_call_ms": round(f64["t_force_s"] * 1e3, 4)},
+                 "rho_kernel_ms": round(f64["t_rho_s"] * 1e3, 4), "force_kernel_ms": round(f64["t_force_s"] * 1e3, 4),
+                 "tiles": f64["tiles"]},
         "fp32_over_fp64_speedup": round(f64["wall_s"] / f32["wall_s"], 3),
-        "fp32_calls_ms": {"rho_call": round(f32["t_rho_s"] * 1e3, 4), "force_call": round(f32["t_force_s"] * 1e3, 4)},
-        "roofline": {"bound": "alu", "kernel": "rho_f32_kernel (+reduce)" if dom == "rho" else "force_f32_kernel",
+        "fp32_kernels_ms": {"rho_kernel": round(f32["t_rho_s"] * 1e3, 4), "force_kernel": round(f32["t_force_s"] * 1e3, 4),
+                            "tiles": f32["tiles"]},
+        "roofline": {"bound": "alu", "kernel": "rho_f32_kernel" if dom == "rho" else "force_f32_kernel",
                      "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
                      "frac": round(achieved / peak, 4), "traffic": None,
                      "ops_per_term": slots, "terms_per_launch": terms},
@@ -249,20 +233,21 @@ def bench_batched(torch, ri, Plan, Batch, dev, steps):
     plan = Plan(batch, precision="fp32_mixed")
     cat = [torch.tensor(np.concatenate([getattr(x, a) for x in systems]), dtype=torch.float64, device=dev)
            for a in ("x", "y", "z", "q")]
-    m, w = plan.sample_k_device(6000, 0)
-    for k in range(3):
-        plan.sample_k_device(6000, k, m, w)
-        plan.forward(*cat, m, w)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(steps):
-        plan.sample_k_device(6000, k, m, w)
-        plan.forward(*cat, m, w)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        counter = torch.zeros(1, dtype=torch.int64, device=dev)
+        g = plan.graph(*cat, seed=6000, stream_base=0, step_counter=counter)
+        for k in range(3):
+            g.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            g.launch()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
     terms = sum(x.n for x in systems) * reps.P
-    return {"batched_128_replicas_fp32_mixed": {"ms_per_step": dt * 1e3, "G_terms_per_s": terms / dt / 1e9,
-                                                "N_total": int(sum(x.n for x in systems))}}
+    return {"batched_128_replicas_fp32_mixed_graph": {"ms_per_step": dt * 1e3, "G_terms_per_s": terms / dt / 1e9,
+                                                      "N_total": int(sum(x.n for x in systems)), "tiles": plan.tiles()}}
 
 
 if __name__ == "__main__":

@@ -84,6 +84,7 @@ typedef enum {
 } rbe_phase_mode;
 
 typedef struct rbe_plan rbe_plan;   /* opaque; host memory owned by the library */
+typedef struct rbe_graph rbe_graph; /* opaque; an instantiated HIP graph of one evaluation */
 
 /* ---------------------------------------------------------------- host-only calls */
 
@@ -129,12 +130,30 @@ size_t rbe_plan_workspace_bytes(const rbe_plan *plan);
 /*
  * Select kernel variants (autotuner hook).  rho_variant and force_variant
  * index the variant tables reported by rbe_plan_num_variants; -1 keeps the
- * current choice.  Changes the workspace layout: query the size and upload
- * again afterwards.
+ * current choice.  The workspace size covers every variant, but its contents
+ * change: call rbe_plan_upload again before the next device call.
  */
 rbe_status rbe_plan_set_tiles(rbe_plan *plan, int32_t rho_variant, int32_t force_variant);
 rbe_status rbe_plan_num_variants(const rbe_plan *plan, int32_t *n_rho, int32_t *n_force);
 rbe_status rbe_plan_get_tiles(const rbe_plan *plan, int32_t *rho_variant, int32_t *force_variant);
+
+/*
+ * Persistent grids: launch at most rho_cap blocks for the rho-shaped passes and
+ * force_cap blocks for the force-shaped passes, each block striding over the
+ * work items (0, the default: one block per work item).  Results do not
+ * depend on the caps.
+ */
+rbe_status rbe_plan_set_grid_caps(rbe_plan *plan, int32_t rho_cap, int32_t force_cap);
+
+/*
+ * Kernel timing hook: when set (non-NULL hipEvent_t handles), every later call
+ * records rho_begin / rho_end on its stream right before / after the rho-pass
+ * kernel (the cross-tile reduction is outside the pair) and force_begin /
+ * force_end around the force-pass kernel.  NULL clears a slot.  The events
+ * belong to the caller.
+ */
+rbe_status rbe_plan_set_timing_events(rbe_plan *plan, void *rho_begin, void *rho_end,
+                                      void *force_begin, void *force_end);
 
 /* Release the plan (host memory only). */
 void rbe_plan_destroy(rbe_plan *plan);
@@ -193,6 +212,37 @@ rbe_status rbe_kspace_vjp(const rbe_plan *plan, const double *x, const double *y
  */
 rbe_status rbe_sample_k_device(const rbe_plan *plan, uint64_t seed, uint64_t stream_id,
                                int32_t *m, double *w, void *ws, void *stream);
+
+/*
+ * Autotuner: time every rho-pass variant on rbe_structure_factor and every
+ * force-pass variant on rbe_kspace_force with the caller's inputs (reps timed
+ * runs each after one warm-up, HIP events on `stream`), keep the fastest of
+ * each, upload the plan again and report the choice and its mean times in ms
+ * (any output pointer may be NULL).  Arguments as for the calls it times; rho,
+ * F and U are overwritten.  Synchronises `stream`.
+ */
+rbe_status rbe_plan_tune(rbe_plan *plan, const double *x, const double *y, const double *z,
+                         const double *q, const int32_t *m, const double *w, double *rho, void *F,
+                         double *U, void *ws, void *stream, int32_t reps, int32_t *rho_variant,
+                         int32_t *force_variant, double *rho_ms, double *force_ms);
+
+/*
+ * Capture one whole evaluation of every system of the plan -- device sampling
+ * (rbe_sample_k_device), rbe_structure_factor and rbe_kspace_force -- into a
+ * HIP graph, for replay with rbe_graph_launch at the cost of one launch.
+ * The graph records the pointers given here; replays read the buffers' current
+ * contents (update positions in place between replays).  step_counter (dev, one
+ * uint64, may be NULL): the sampler of system b uses stream id
+ * stream_base + *step_counter and the force pass adds 1 to it, so every replay
+ * draws new wave vectors (NULL: every replay uses stream_base).  The plan and
+ * the workspace must stay alive and uploaded while the graph is used.
+ */
+rbe_status rbe_graph_create(const rbe_plan *plan, uint64_t seed, uint64_t stream_base,
+                            uint64_t *step_counter, const double *x, const double *y,
+                            const double *z, const double *q, int32_t *m, double *w, double *rho,
+                            void *F, double *U, void *ws, rbe_graph **out);
+rbe_status rbe_graph_launch(const rbe_graph *graph, void *stream);
+void rbe_graph_destroy(rbe_graph *graph);
 
 /* ---------------------------------------------------------------- diagnostics */
 

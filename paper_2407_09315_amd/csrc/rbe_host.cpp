@@ -99,6 +99,9 @@ struct rbe_plan {
   bool cached = false;
   int rho_variant = 0;
   int force_variant = 1;
+  int32_t rho_grid_cap = 0;     // 0: one block per work item
+  int32_t force_grid_cap = 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // optional kernel timing events
   bool sampler_ok = true;
 
   // host copies of the device tables
@@ -110,6 +113,7 @@ struct rbe_plan {
   // workspace layout (byte offsets)
   size_t off_sys = 0, off_rho = 0, off_force = 0, off_ksys = 0, off_cdf = 0, off_part = 0,
          off_xy = 0, off_cache = 0, total = 0;
+  size_t ws_bytes = 0;      // workspace size: the largest layout over all variants
   int64_t n_partials = 0;   // complex slots
   int64_t n_cache = 0;      // (cos, sin) pairs
 
@@ -118,6 +122,11 @@ struct rbe_plan {
   RhoVariant rv() const {
     return precision == RBE_FP32_MIXED ? kRhoVariantsF32[rho_variant] : kRhoVariantsF64[rho_variant];
   }
+};
+
+struct rbe_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -220,6 +229,14 @@ LaunchShape shape_of(const rbe_plan* p) {
   s.rho_variant = p->rho_variant;
   s.fv = kForceVariants[p->force_variant];
   s.force_variant = p->force_variant;
+  s.max_cdf_len = 0;
+  for (const SysDesc& d : p->sys) s.max_cdf_len = std::max(s.max_cdf_len, d.cdf_len);
+  s.rho_grid_cap = p->rho_grid_cap;
+  s.force_grid_cap = p->force_grid_cap;
+  s.ev_rho_begin = p->ev[0];
+  s.ev_rho_end = p->ev[1];
+  s.ev_force_begin = p->ev[2];
+  s.ev_force_end = p->ev[3];
   return s;
 }
 
@@ -338,6 +355,18 @@ rbe_status rbe_plan_create(int32_t B, const int64_t* sys_off, const int64_t* k_o
   p->phase_mode = phase_mode;
   // Measured: recomputing phases beats the HBM phase cache at every benchmarked shape.
   p->cached = phase_mode == RBE_PHASE_CACHED;
+  // The workspace is sized for the largest layout over all variants, so the
+  // autotuner can switch variants without reallocating.
+  const int nr = precision == RBE_FP32_MIXED ? kNumRhoVariantsF32 : kNumRhoVariantsF64;
+  size_t most = 0;
+  for (int r = 0; r < nr; ++r)
+    for (int f = 0; f < kNumForceVariants; ++f) {
+      p->rho_variant = r;
+      p->force_variant = f;
+      build_layout(p);
+      most = std::max(most, p->total);
+    }
+  p->ws_bytes = most;
   p->rho_variant = 0;
   p->force_variant = 1;
   build_layout(p);
@@ -345,7 +374,7 @@ rbe_status rbe_plan_create(int32_t B, const int64_t* sys_off, const int64_t* k_o
   return RBE_OK;
 }
 
-size_t rbe_plan_workspace_bytes(const rbe_plan* p) { return p ? p->total : 0; }
+size_t rbe_plan_workspace_bytes(const rbe_plan* p) { return p ? p->ws_bytes : 0; }
 
 rbe_status rbe_plan_num_variants(const rbe_plan* p, int32_t* n_rho, int32_t* n_force) {
   if (!p || !n_rho || !n_force) return fail(RBE_EINVAL, "NULL argument");
@@ -418,7 +447,7 @@ rbe_status rbe_kspace_force(const rbe_plan* p, const double* x, const double* y,
     return fail(RBE_EINVAL, "NULL position/charge/force array");
   if (!need(m, P) || !need(w, P) || !need(rho, P)) return fail(RBE_EINVAL, "NULL m, w or rho array");
   if (U == nullptr) return fail(RBE_EINVAL, "U is NULL");
-  hipError_t e = launch_force(shape_of(p), view_of(p, ws), x, y, z, q, m, w, rho, F, U,
+  hipError_t e = launch_force(shape_of(p), view_of(p, ws), x, y, z, q, m, w, rho, F, U, nullptr,
                               static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "force pass launch");
   return RBE_OK;
@@ -440,6 +469,140 @@ rbe_status rbe_kspace_vjp(const rbe_plan* p, const double* x, const double* y, c
   return RBE_OK;
 }
 
+rbe_status rbe_plan_tune(rbe_plan* p, const double* x, const double* y, const double* z, const double* q,
+                         const int32_t* m, const double* w, double* rho, void* F, double* U, void* ws,
+                         void* stream, int32_t reps, int32_t* rho_variant, int32_t* force_variant,
+                         double* rho_ms, double* force_ms) {
+  rbe_status st = check_common(p, ws);
+  if (st != RBE_OK) return st;
+  if (reps <= 0) return fail(RBE_EINVAL, "reps must be > 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(RBE_EHIP, "hipEventCreate failed");
+  auto timed = [&](bool force_pass, float* ms) -> rbe_status {
+    rbe_status r = rbe_plan_upload(p, ws, stream);
+    if (r != RBE_OK) return r;
+    for (int i = 0; i <= reps; ++i) {   // the first run is a warm-up
+      if (i == 1 && hipEventRecord(e0, s) != hipSuccess) return fail(RBE_EHIP, "hipEventRecord failed");
+      r = force_pass ? rbe_kspace_force(p, x, y, z, q, m, w, rho, F, U, ws, stream)
+                     : rbe_structure_factor(p, x, y, z, q, m, rho, ws, stream);
+      if (r != RBE_OK) return r;
+    }
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      return fail(RBE_EHIP, "event wait failed");
+    if (hipEventElapsedTime(ms, e0, e1) != hipSuccess) return fail(RBE_EHIP, "hipEventElapsedTime failed");
+    *ms /= (float)reps;
+    return RBE_OK;
+  };
+  const int nr = p->precision == RBE_FP32_MIXED ? kNumRhoVariantsF32 : kNumRhoVariantsF64;
+  int best_r = p->rho_variant, best_f = p->force_variant;
+  float best_rms = 1e30f, best_fms = 1e30f;
+  rbe_status r = RBE_OK;
+  for (int v = 0; v < nr && r == RBE_OK; ++v) {
+    p->rho_variant = v;
+    build_layout(p);
+    float ms = 0.f;
+    r = timed(false, &ms);
+    if (r == RBE_OK && ms < best_rms) { best_rms = ms; best_r = v; }
+  }
+  p->rho_variant = best_r;
+  for (int v = 0; v < kNumForceVariants && r == RBE_OK; ++v) {
+    p->force_variant = v;
+    build_layout(p);
+    float ms = 0.f;
+    // the force pass needs rho of the current layout
+    r = rbe_plan_upload(p, ws, stream);
+    if (r == RBE_OK) r = rbe_structure_factor(p, x, y, z, q, m, rho, ws, stream);
+    if (r == RBE_OK) r = timed(true, &ms);
+    if (r == RBE_OK && ms < best_fms) { best_fms = ms; best_f = v; }
+  }
+  p->force_variant = best_f;
+  build_layout(p);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (r != RBE_OK) return r;
+  r = rbe_plan_upload(p, ws, stream);
+  if (r != RBE_OK) return r;
+  if (rho_variant) *rho_variant = best_r;
+  if (force_variant) *force_variant = best_f;
+  if (rho_ms) *rho_ms = best_rms;
+  if (force_ms) *force_ms = best_fms;
+  return RBE_OK;
+}
+
+rbe_status rbe_plan_set_grid_caps(rbe_plan* p, int32_t rho_cap, int32_t force_cap) {
+  if (!p) return fail(RBE_EINVAL, "plan is NULL");
+  if (rho_cap < 0 || force_cap < 0) return fail(RBE_EINVAL, "grid caps must be >= 0");
+  p->rho_grid_cap = rho_cap;
+  p->force_grid_cap = force_cap;
+  return RBE_OK;
+}
+
+rbe_status rbe_plan_set_timing_events(rbe_plan* p, void* rho_begin, void* rho_end, void* force_begin,
+                                      void* force_end) {
+  if (!p) return fail(RBE_EINVAL, "plan is NULL");
+  p->ev[0] = static_cast<hipEvent_t>(rho_begin);
+  p->ev[1] = static_cast<hipEvent_t>(rho_end);
+  p->ev[2] = static_cast<hipEvent_t>(force_begin);
+  p->ev[3] = static_cast<hipEvent_t>(force_end);
+  return RBE_OK;
+}
+
+rbe_status rbe_graph_create(const rbe_plan* p, uint64_t seed, uint64_t stream_base, uint64_t* step_counter,
+                            const double* x, const double* y, const double* z, const double* q, int32_t* m,
+                            double* w, double* rho, void* F, double* U, void* ws, rbe_graph** out) {
+  if (out == nullptr) return fail(RBE_EINVAL, "out is NULL");
+  *out = nullptr;
+  rbe_status st = check_common(p, ws);
+  if (st != RBE_OK) return st;
+  if (!p->sampler_ok) return fail(RBE_EINVAL, "a system's zero-vector probability exceeds 1/2 (box too small for alpha)");
+  const int64_t n = p->n_total(), P = p->p_total();
+  if (!need(x, n) || !need(y, n) || !need(z, n) || !need(q, n) || !need(F, n))
+    return fail(RBE_EINVAL, "NULL position/charge/force array");
+  if (!need(m, P) || !need(w, P) || !need(rho, P) || U == nullptr) return fail(RBE_EINVAL, "NULL m, w, rho or U");
+  hipStream_t cs;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+  const LaunchShape shape = shape_of(p);
+  const WsView view = view_of(p, ws);
+  hipGraph_t graph = nullptr;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    hipError_t le = launch_sample(shape, view, seed, stream_base, step_counter, m, w, cs);
+    if (le == hipSuccess) le = launch_rho(shape, view, x, y, z, q, m, rho, cs);
+    if (le == hipSuccess) le = launch_force(shape, view, x, y, z, q, m, w, rho, F, U, step_counter, cs);
+    e = hipStreamEndCapture(cs, &graph);
+    if (le != hipSuccess) e = le;
+  }
+  hipGraphExec_t exec = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return hip_fail(e, "graph capture");
+  }
+  rbe_graph* g = new rbe_graph();
+  g->graph = graph;
+  g->exec = exec;
+  *out = g;
+  return RBE_OK;
+}
+
+rbe_status rbe_graph_launch(const rbe_graph* g, void* stream) {
+  if (g == nullptr) return fail(RBE_EINVAL, "graph is NULL");
+  hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return RBE_OK;
+}
+
+void rbe_graph_destroy(rbe_graph* g) {
+  if (g == nullptr) return;
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
 rbe_status rbe_sample_k_device(const rbe_plan* p, uint64_t seed, uint64_t stream_id, int32_t* m, double* w,
                                void* ws, void* stream) {
   rbe_status st = check_common(p, ws);
@@ -447,7 +610,8 @@ rbe_status rbe_sample_k_device(const rbe_plan* p, uint64_t seed, uint64_t stream
   if (!p->sampler_ok) return fail(RBE_EINVAL, "a system's zero-vector probability exceeds 1/2 (box too small for alpha)");
   const int64_t P = p->p_total();
   if (!need(m, P) || !need(w, P)) return fail(RBE_EINVAL, "NULL m or w array");
-  hipError_t e = launch_sample(shape_of(p), view_of(p, ws), seed, stream_id, m, w, static_cast<hipStream_t>(stream));
+  hipError_t e = launch_sample(shape_of(p), view_of(p, ws), seed, stream_id, nullptr, m, w,
+                               static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "sampler launch");
   return RBE_OK;
 }

@@ -44,8 +44,8 @@ struct ForceItem {
 struct RhoVariant { int npl; int kc; int krange; };   // particles per lane, k per chunk, k per item
 struct ForceVariant { int nplf; };                       // particles per lane (256-thread blocks)
 
-constexpr int kNumRhoVariantsF32 = 4;
-constexpr int kNumRhoVariantsF64 = 3;
+constexpr int kNumRhoVariantsF32 = 6;
+constexpr int kNumRhoVariantsF64 = 5;
 constexpr int kNumForceVariants = 3;
 extern const RhoVariant kRhoVariantsF32[kNumRhoVariantsF32];
 extern const RhoVariant kRhoVariantsF64[kNumRhoVariantsF64];
@@ -79,6 +79,11 @@ struct LaunchShape {
   int rho_variant;
   ForceVariant fv;
   int force_variant;
+  int32_t max_cdf_len;   // longest sampler table of the plan
+  int32_t rho_grid_cap;  // persistent-grid caps (0: one block per work item)
+  int32_t force_grid_cap;
+  // optional events recorded right before / after the rho-pass and force-pass kernels
+  hipEvent_t ev_rho_begin, ev_rho_end, ev_force_begin, ev_force_end;
 };
 
 // Kernel launchers (rbe_kernels.hip).  Each returns hipSuccess or the launch error.
@@ -87,12 +92,12 @@ hipError_t launch_rho(const LaunchShape& s, const WsView& w, const double* x, co
                       hipStream_t st);
 hipError_t launch_force(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                         const double* z, const double* q, const int32_t* m, const double* wk,
-                        const double* rho, void* F, double* U, hipStream_t st);
+                        const double* rho, void* F, double* U, uint64_t* counter, hipStream_t st);
 hipError_t launch_vjp(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                       const double* z, const double* q, const int32_t* m, const double* wk,
                       const double* rho, const double* gU, const void* gF, void* gr, void* gq,
                       hipStream_t st);
 hipError_t launch_sample(const LaunchShape& s, const WsView& w, uint64_t seed, uint64_t stream_id,
-                         int32_t* m, double* wk, hipStream_t st);
+                         const uint64_t* counter, int32_t* m, double* wk, hipStream_t st);
 
 }  // namespace rbe

@@ -23,14 +23,19 @@
 // after an exact quarter-turn reduction.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "philox.h"
 #include "rbe_internal.h"
 #include "sincos_coeffs.h"
 
 namespace rbe {
 
-const RhoVariant kRhoVariantsF32[kNumRhoVariantsF32] = {{16, 8, 56}, {8, 8, 104}, {16, 8, 104}, {8, 8, 56}};
-const RhoVariant kRhoVariantsF64[kNumRhoVariantsF64] = {{8, 4, 52}, {4, 4, 100}, {8, 4, 100}};
+// {particles per lane, wave vectors per chunk, wave vectors per work item}
+const RhoVariant kRhoVariantsF32[kNumRhoVariantsF32] = {
+    {16, 8, 56}, {8, 8, 104}, {16, 4, 52}, {32, 2, 50}, {12, 8, 104}, {24, 4, 52}};
+const RhoVariant kRhoVariantsF64[kNumRhoVariantsF64] = {
+    {8, 4, 52}, {4, 4, 100}, {8, 4, 100}, {4, 8, 104}, {8, 2, 50}};
 const ForceVariant kForceVariants[kNumForceVariants] = {{1}, {2}, {4}};
 
 namespace {
@@ -38,6 +43,7 @@ namespace {
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kFourPi = 12.566370614359172953850573533118;
 constexpr int kTabChunk = 256;
+constexpr int kUnroll = 4;   // table rows per step of the force-shaped passes
 
 // ------------------------------------------------------------------ phase helpers
 
@@ -87,33 +93,97 @@ __device__ inline double phase_f64(double mx, double my, double mz, double sx, d
 
 // ------------------------------------------------------------------ wave reductions
 
-__device__ inline int bitrev(int v, int bits) {
-  int r = 0;
-  for (int b = 0; b < bits; ++b) r |= ((v >> b) & 1) << (bits - 1 - b);
-  return r;
-}
-
 template <int V> struct Log2 { static constexpr int value = 1 + Log2<V / 2>::value; };
 template <> struct Log2<1> { static constexpr int value = 0; };
 
-// Recursive-halving reduce-scatter of V values per lane over the 64 lanes of a wave.
-// Afterwards v[0] of lane L holds the wave sum of value index bitrev(L mod V).
-template <int V, typename T>
-__device__ inline void wave_reduce_scatter(T (&v)[V], int lane) {
-  static_assert((V & (V - 1)) == 0 && V <= 64, "V must be a power of two <= 64");
+// Cross-lane exchange with a DPP row permutation (VALU, no LDS round trip).
+template <int CTRL>
+__device__ inline float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const int2 a = *reinterpret_cast<const int2*>(&v);
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(0, a.x, CTRL, 0xF, 0xF, false);
+  r.y = __builtin_amdgcn_update_dpp(0, a.y, CTRL, 0xF, 0xF, false);
+  return *reinterpret_cast<const double*>(&r);
+}
+
+// DPP controls of the four in-row reduce-scatter levels and the lane bit that
+// selects the kept half at each level.  Partners: lane ^ 1 and lane ^ 2 (quad
+// permutations), lane ^ 7 within 8 (half-row mirror), lane ^ 8 within 16 (row
+// rotation by 8).  The kept-half selectors s1 = b0^b2, s2 = b1^b2, s3 = b2,
+// s4 = b3 make every pair of partners hold the same value subset.
+constexpr int kDppCtrl[4] = {0xB1, 0x4E, 0x141, 0x128};
+
+__device__ inline bool keep_upper(int level, int lane) {
+  const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+  switch (level) {
+    case 0: return (b0 ^ b2) != 0;
+    case 1: return (b1 ^ b2) != 0;
+    case 2: return b2 != 0;
+    default: return b3 != 0;
+  }
+}
+
+// Value index that lane L holds after the in-row levels (inverse of the selectors).
+__device__ inline int scatter_index(int lane, int levels) {
+  int idx = 0;
+  for (int j = 0; j < levels; ++j) idx = 2 * idx + (keep_upper(j, lane) ? 1 : 0);
+  return idx;
+}
+
+template <int LEVEL, int HALF, typename T, int V>
+struct ReduceScatter {
+  __device__ static inline void run(T (&v)[V], int lane) {
+    const bool upper = keep_upper(LEVEL, lane);
 #pragma unroll
-  for (int lvl = 0, half = V / 2; half >= 1; ++lvl, half /= 2) {
-    const int b = 1 << lvl;
-    const bool upper = (lane & b) != 0;
-#pragma unroll
-    for (int i = 0; i < half; ++i) {
-      const T send = upper ? v[i] : v[i + half];
-      const T keep = upper ? v[i + half] : v[i];
-      v[i] = keep + __shfl_xor(send, b, 64);
+    for (int i = 0; i < HALF; ++i) {
+      const T send = upper ? v[i] : v[i + HALF];
+      const T keep = upper ? v[i + HALF] : v[i];
+      v[i] = keep + dpp_move<kDppCtrl[LEVEL]>(send);
+    }
+    ReduceScatter<LEVEL + 1, HALF / 2, T, V>::run(v, lane);
+  }
+};
+template <int LEVEL, typename T, int V>
+struct ReduceScatter<LEVEL, 0, T, V> {
+  __device__ static inline void run(T (&v)[V], int lane) {
+    if constexpr (LEVEL < 4) {
+      // remaining in-row levels: the partners already hold the same value index
+      v[0] += dpp_move<kDppCtrl[LEVEL]>(v[0]);
+      ReduceScatter<LEVEL + 1, 0, T, V>::run(v, lane);
+    } else {
+      // sum the four rows of 16 lanes
+      v[0] += __shfl_xor(v[0], 16, 64);
+      v[0] += __shfl_xor(v[0], 32, 64);
     }
   }
+};
+
+// Reduce-scatter of V values per lane over the 64 lanes of a wave: afterwards v[0] of
+// lane L holds the wave sum of value index scatter_index(L mod 16, log2 V).  Every
+// index is a compile-time constant, so the values stay in registers.
+template <int V, typename T>
+__device__ inline void wave_reduce_scatter(T (&v)[V], int lane) {
+  static_assert(V == 2 || V == 4 || V == 8 || V == 16, "V must be 2, 4, 8 or 16");
+  ReduceScatter<0, V / 2, T, V>::run(v, lane);
+}
+
+// Wave vectors kc .. kc+KC-1 of an item (zero past its end); uniform, so scalar loads.
+template <int KC>
+__device__ inline void load_chunk(const int32_t* mk, int kc, int nk, int32_t (&mx)[KC], int32_t (&my)[KC],
+                                  int32_t (&mz)[KC]) {
 #pragma unroll
-  for (int b = V; b < 64; b *= 2) v[0] += __shfl_xor(v[0], b, 64);
+  for (int c = 0; c < KC; ++c) {
+    const int kk = min(kc + c, nk - 1);
+    const int32_t a = mk[3 * kk], b = mk[3 * kk + 1], d = mk[3 * kk + 2];
+    const bool ok = kc + c < nk;
+    mx[c] = ok ? a : 0;
+    my[c] = ok ? b : 0;
+    mz[c] = ok ? d : 0;
+  }
 }
 
 // ------------------------------------------------------------------ rho pass, FP32-mixed
@@ -126,8 +196,10 @@ __global__ __launch_bounds__(64) void rho_f32_kernel(WsView w, const double* __r
                                                      const double* __restrict__ z,
                                                      const double* __restrict__ q,
                                                      const int32_t* __restrict__ m,
-                                                     const float* __restrict__ gF, int64_t n_total) {
-  const RhoItem it = w.rho_items[blockIdx.x];
+                                                     const float* __restrict__ gF, int64_t n_total,
+                                                     int32_t n_items) {
+for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+  const RhoItem it = w.rho_items[item];
   const SysDesc sd = w.sys[it.sys];
   const int lane = threadIdx.x;
   const int first = it.tile * (64 * NPL);
@@ -159,43 +231,50 @@ __global__ __launch_bounds__(64) void rho_f32_kernel(WsView w, const double* __r
   double* part = w.partials + 2 * sd.part_off;
   const int32_t* mk = m + 3 * (sd.k_off + it.k0);
 
+  // wave vectors of the next chunk are loaded (scalar loads) one chunk ahead
+  int32_t nmx[KC], nmy[KC], nmz[KC];
+  load_chunk<KC>(mk, 0, it.nk, nmx, nmy, nmz);
   for (int kc = 0; kc < it.nk; kc += KC) {
     int32_t mx[KC], my[KC], mz[KC];
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
-      const bool ok = kc + c < it.nk;
-      const int kk = ok ? kc + c : it.nk - 1;
-      mx[c] = ok ? mk[3 * kk] : 0;
-      my[c] = ok ? mk[3 * kk + 1] : 0;
-      mz[c] = ok ? mk[3 * kk + 2] : 0;
+      mx[c] = nmx[c];
+      my[c] = nmy[c];
+      mz[c] = nmz[c];
     }
+    if (kc + KC < it.nk) load_chunk<KC>(mk, kc + KC, it.nk, nmx, nmy, nmz);
     float acc[2 * KC];
 #pragma unroll
     for (int c = 0; c < 2 * KC; ++c) acc[c] = 0.0f;
 #pragma unroll
     for (int j = 0; j < NPL; ++j) {
+      // one particle against the KC wave vectors, stage by stage for instruction-level parallelism
+      float a[KC], sn[KC], cs[KC];
+#pragma unroll
+      for (int c = 0; c < KC; ++c) a[c] = turns_arg(phase_u32(mx[c], my[c], mz[c], ux[j], uy[j], uz[j]));
+#pragma unroll
+      for (int c = 0; c < KC; ++c) sn[c] = __builtin_amdgcn_sinf(a[c]);
+#pragma unroll
+      for (int c = 0; c < KC; ++c) cs[c] = __builtin_amdgcn_cosf(a[c]);
 #pragma unroll
       for (int c = 0; c < KC; ++c) {
-        const float a = turns_arg(phase_u32(mx[c], my[c], mz[c], ux[j], uy[j], uz[j]));
-        const float sn = __builtin_amdgcn_sinf(a);
-        const float cs = __builtin_amdgcn_cosf(a);
         float wt = qv[j];
         if (VJP) wt = fmaf(qgx[j], (float)mx[c], fmaf(qgy[j], (float)my[c], qgz[j] * (float)mz[c]));
-        acc[c] = fmaf(wt, cs, acc[c]);
-        acc[KC + c] = fmaf(wt, sn, acc[KC + c]);
+        acc[c] = fmaf(wt, cs[c], acc[c]);
+        acc[KC + c] = fmaf(wt, sn[c], acc[KC + c]);
         if (CACHE) {
           const int li = j * 64 + lane;
           if (li < cnt && kc + c < it.nk) {
             float2* cp = reinterpret_cast<float2*>(w.cache) + sd.cache_off +
                          (int64_t)(it.k0 + kc + c) * sd.n + first + li;
-            *cp = make_float2(cs, sn);
+            *cp = make_float2(cs[c], sn[c]);
           }
         }
       }
     }
     wave_reduce_scatter<2 * KC>(acc, lane);
     if (lane < 2 * KC) {
-      const int vi = bitrev(lane, Log2<2 * KC>::value);
+      const int vi = scatter_index(lane, Log2<2 * KC>::value);
       const int c = vi % KC;
       const int comp = vi / KC;
       if (kc + c < it.nk) {
@@ -203,6 +282,7 @@ __global__ __launch_bounds__(64) void rho_f32_kernel(WsView w, const double* __r
         part[2 * (kl * sd.ntiles + it.tile) + comp] = (double)acc[0];
       }
     }
+  }
   }
 }
 
@@ -214,8 +294,10 @@ __global__ __launch_bounds__(64) void rho_f64_kernel(WsView w, const double* __r
                                                      const double* __restrict__ z,
                                                      const double* __restrict__ q,
                                                      const int32_t* __restrict__ m,
-                                                     const double* __restrict__ gF, int64_t n_total) {
-  const RhoItem it = w.rho_items[blockIdx.x];
+                                                     const double* __restrict__ gF, int64_t n_total,
+                                                     int32_t n_items) {
+for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+  const RhoItem it = w.rho_items[item];
   const SysDesc sd = w.sys[it.sys];
   const int lane = threadIdx.x;
   const int first = it.tile * (64 * NPL);
@@ -252,11 +334,12 @@ __global__ __launch_bounds__(64) void rho_f64_kernel(WsView w, const double* __r
     double mx[KC], my[KC], mz[KC];
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
+      const int kk = min(kc + c, it.nk - 1);
+      const int32_t a = mk[3 * kk], b = mk[3 * kk + 1], d = mk[3 * kk + 2];
       const bool ok = kc + c < it.nk;
-      const int kk = ok ? kc + c : it.nk - 1;
-      mx[c] = ok ? (double)mk[3 * kk] : 0.0;
-      my[c] = ok ? (double)mk[3 * kk + 1] : 0.0;
-      mz[c] = ok ? (double)mk[3 * kk + 2] : 0.0;
+      mx[c] = ok ? (double)a : 0.0;
+      my[c] = ok ? (double)b : 0.0;
+      mz[c] = ok ? (double)d : 0.0;
     }
     double acc[2 * KC];
 #pragma unroll
@@ -275,7 +358,7 @@ __global__ __launch_bounds__(64) void rho_f64_kernel(WsView w, const double* __r
     }
     wave_reduce_scatter<2 * KC>(acc, lane);
     if (lane < 2 * KC) {
-      const int vi = bitrev(lane, Log2<2 * KC>::value);
+      const int vi = scatter_index(lane, Log2<2 * KC>::value);
       const int c = vi % KC;
       const int comp = vi / KC;
       if (kc + c < it.nk) {
@@ -284,32 +367,40 @@ __global__ __launch_bounds__(64) void rho_f64_kernel(WsView w, const double* __r
       }
     }
   }
+  }
 }
 
 // ------------------------------------------------------------------ cross-tile reduction
 
-// One wave per wave vector: out[g] = sum over the system's tiles of partial[g][tile],
-// lanes stride the tiles, then a fixed butterfly; optionally rotated by exp(i delta).
-__global__ __launch_bounds__(kReduceBlock) void reduce_kernel(WsView w, int64_t p_total,
-                                                              double* __restrict__ out,
+// One block per wave vector: out[g] = sum over the system's tiles of partial[g][tile].
+// Thread t sums tiles t, t + 256, ... in order, then a fixed tree over the block;
+// the result is optionally rotated by exp(i delta).
+__global__ __launch_bounds__(kReduceBlock) void reduce_kernel(WsView w, double* __restrict__ out,
                                                               double rot_c, double rot_s) {
-  const int lane = threadIdx.x & 63;
-  const int64_t g = (int64_t)blockIdx.x * (kReduceBlock / 64) + (threadIdx.x >> 6);
-  if (g >= p_total) return;
+  __shared__ double red_re[kReduceBlock], red_im[kReduceBlock];
+  const int64_t g = blockIdx.x;
+  const int tid = threadIdx.x;
   const SysDesc sd = w.sys[w.ksys[g]];
   const int64_t l = g - sd.k_off;
   const double* src = w.partials + 2 * (sd.part_off + l * sd.ntiles);
   double re = 0.0, im = 0.0;
-  for (int t = lane; t < sd.ntiles; t += 64) {
+  for (int t = tid; t < sd.ntiles; t += kReduceBlock) {
     re += src[2 * t];
     im += src[2 * t + 1];
   }
-#pragma unroll
-  for (int b = 32; b >= 1; b >>= 1) {
-    re += __shfl_xor(re, b, 64);
-    im += __shfl_xor(im, b, 64);
+  red_re[tid] = re;
+  red_im[tid] = im;
+  __syncthreads();
+  for (int h = kReduceBlock / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      red_re[tid] += red_re[tid + h];
+      red_im[tid] += red_im[tid + h];
+    }
+    __syncthreads();
   }
-  if (lane == 0) {
+  if (tid == 0) {
+    re = red_re[0];
+    im = red_im[0];
     out[2 * g] = re * rot_c - im * rot_s;
     out[2 * g + 1] = re * rot_s + im * rot_c;
   }
@@ -342,10 +433,11 @@ __global__ __launch_bounds__(kForceBlock) void force_f32_kernel(
     WsView w, int64_t n_total, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const double* __restrict__ q, const int32_t* __restrict__ m,
     const double* __restrict__ wk, const double* __restrict__ rho, float* __restrict__ F,
-    double* __restrict__ U, double rot_c, double rot_s) {
+    double* __restrict__ U, double rot_c, double rot_s, int32_t n_items, uint64_t* __restrict__ counter) {
   __shared__ TabF32 tab[kTabChunk];
   __shared__ double red[kForceBlock];
-  const ForceItem it = w.force_items[blockIdx.x];
+for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+  const ForceItem it = w.force_items[item];
   const SysDesc sd = w.sys[it.sys];
   const int tid = threadIdx.x;
   const double invL = 1.0 / sd.L;
@@ -389,29 +481,44 @@ __global__ __launch_bounds__(kForceBlock) void force_f32_kernel(
       tab[e] = tb;
       if (it.flags & 1) usum += 0.5 * c * (C * C + S * S);
     }
+    // zero rows pad the chunk to a multiple of kUnroll (m = 0, a = b = 0: no contribution)
+    const int cntp = (cnt + kUnroll - 1) / kUnroll * kUnroll;
+    for (int e = cnt + tid; e < cntp; e += kForceBlock) tab[e] = TabF32{0, 0, 0, 0.f, 0.f, 0.f, 0.f, 0.f};
     __syncthreads();
-    for (int e = 0; e < cnt; ++e) {
-      const TabF32 tb = tab[e];
+    for (int e = 0; e < cntp; e += kUnroll) {
+      TabF32 tb[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) tb[u] = tab[e + u];
 #pragma unroll
       for (int j = 0; j < NPLF; ++j) {
-        float sn, cs;
+        float sn[kUnroll], cs[kUnroll];
         if (CACHED) {
-          if (j * kForceBlock + tid < it.np) {
-            const float2 v = reinterpret_cast<const float2*>(w.cache)[sd.cache_off + (int64_t)(t0 + e) * sd.n + li[j]];
-            cs = v.x;
-            sn = v.y;
-          } else {
-            cs = sn = 0.0f;
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            if (j * kForceBlock + tid < it.np && e + u < cnt) {
+              const float2 v = reinterpret_cast<const float2*>(w.cache)[sd.cache_off + (int64_t)(t0 + e + u) * sd.n + li[j]];
+              cs[u] = v.x;
+              sn[u] = v.y;
+            } else {
+              cs[u] = sn[u] = 0.0f;
+            }
           }
         } else {
-          const float a = turns_arg(phase_u32(tb.mx, tb.my, tb.mz, ux[j], uy[j], uz[j]));
-          sn = __builtin_amdgcn_sinf(a);
-          cs = __builtin_amdgcn_cosf(a);
+          float a[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) a[u] = turns_arg(phase_u32(tb[u].mx, tb[u].my, tb[u].mz, ux[j], uy[j], uz[j]));
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) sn[u] = __builtin_amdgcn_sinf(a[u]);
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) cs[u] = __builtin_amdgcn_cosf(a[u]);
         }
-        const float g = tb.a * cs - tb.b * sn;
-        fx[j] = fmaf(g, tb.fx, fx[j]);
-        fy[j] = fmaf(g, tb.fy, fy[j]);
-        fz[j] = fmaf(g, tb.fz, fz[j]);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const float g = tb[u].a * cs[u] - tb[u].b * sn[u];
+          fx[j] = fmaf(g, tb[u].fx, fx[j]);
+          fy[j] = fmaf(g, tb[u].fy, fy[j]);
+          fz[j] = fmaf(g, tb[u].fz, fz[j]);
+        }
       }
     }
   }
@@ -427,7 +534,12 @@ __global__ __launch_bounds__(kForceBlock) void force_f32_kernel(
   }
   if (it.flags & 1) {
     const double tot = block_sum(usum, red);
-    if (tid == 0) U[it.sys] = tot;
+    if (tid == 0) {
+      U[it.sys] = tot;
+      // graph replays: advance the device step counter the sampler reads
+      if (counter != nullptr && it.sys == 0) counter[0] += 1;
+    }
+  }
   }
 }
 
@@ -444,10 +556,11 @@ __global__ __launch_bounds__(kForceBlock) void force_f64_kernel(
     WsView w, int64_t n_total, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const double* __restrict__ q, const int32_t* __restrict__ m,
     const double* __restrict__ wk, const double* __restrict__ rho, double* __restrict__ F,
-    double* __restrict__ U) {
+    double* __restrict__ U, int32_t n_items, uint64_t* __restrict__ counter) {
   __shared__ TabF64 tab[kTabChunk];
   __shared__ double red[kForceBlock];
-  const ForceItem it = w.force_items[blockIdx.x];
+for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+  const ForceItem it = w.force_items[item];
   const SysDesc sd = w.sys[it.sys];
   const int tid = threadIdx.x;
   const double invL = 1.0 / sd.L;
@@ -512,7 +625,12 @@ __global__ __launch_bounds__(kForceBlock) void force_f64_kernel(
   }
   if (it.flags & 1) {
     const double tot = block_sum(usum, red);
-    if (tid == 0) U[it.sys] = tot;
+    if (tid == 0) {
+      U[it.sys] = tot;
+      // graph replays: advance the device step counter the sampler reads
+      if (counter != nullptr && it.sys == 0) counter[0] += 1;
+    }
+  }
   }
 }
 
@@ -557,9 +675,10 @@ __global__ __launch_bounds__(kForceBlock) void vjp_b2_f32_kernel(
     const double* __restrict__ z, const double* __restrict__ q, const int32_t* __restrict__ m,
     const double* __restrict__ wk, const double* __restrict__ rho, const double* __restrict__ gU,
     const float* __restrict__ gF, float* __restrict__ gr, float* __restrict__ gq, double rot_c,
-    double rot_s) {
+    double rot_s, int32_t n_items) {
   __shared__ TabAdjF32 tab[kTabChunk];
-  const ForceItem it = w.force_items[blockIdx.x];
+for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+  const ForceItem it = w.force_items[item];
   const SysDesc sd = w.sys[it.sys];
   const int tid = threadIdx.x;
   const double invL = 1.0 / sd.L;
@@ -634,6 +753,7 @@ __global__ __launch_bounds__(kForceBlock) void vjp_b2_f32_kernel(
       gq[gi] = rq[j];
     }
   }
+  }
 }
 
 template <int NPLF>
@@ -641,10 +761,11 @@ __global__ __launch_bounds__(kForceBlock) void vjp_b2_f64_kernel(
     WsView w, int64_t n_total, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const double* __restrict__ q, const int32_t* __restrict__ m,
     const double* __restrict__ wk, const double* __restrict__ rho, const double* __restrict__ gU,
-    const double* __restrict__ gF, double* __restrict__ gr, double* __restrict__ gq) {
+    const double* __restrict__ gF, double* __restrict__ gr, double* __restrict__ gq, int32_t n_items) {
   __shared__ double tabm[kTabChunk][3];
   __shared__ AdjTab tab[kTabChunk];
-  const ForceItem it = w.force_items[blockIdx.x];
+for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+  const ForceItem it = w.force_items[item];
   const SysDesc sd = w.sys[it.sys];
   const int tid = threadIdx.x;
   const double invL = 1.0 / sd.L;
@@ -713,75 +834,113 @@ __global__ __launch_bounds__(kForceBlock) void vjp_b2_f64_kernel(
       gq[gi] = rq[j];
     }
   }
+  }
 }
 
 // ------------------------------------------------------------------ sampler
 
-// One thread per wave vector of every system: Philox key (seed + b, stream_id),
-// counter (l, attempt, 0, 0), inverse CDF per component, zero vector redrawn.
-__global__ __launch_bounds__(256) void sample_kernel(WsView w, int64_t p_total, uint64_t seed,
-                                                     uint64_t stream_id, int32_t* __restrict__ m,
-                                                     double* __restrict__ wk) {
-  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (g >= p_total) return;
-  const int32_t b = w.ksys[g];
+// One block per system, its inverse-CDF table staged in LDS when it fits (else read
+// from the workspace).  Thread t draws wave vectors t, t + 128, ... of the system with
+// Philox key (seed + b, stream_id), counter (l, attempt, 0, 0); a zero vector is redrawn.
+constexpr int kSampleBlock = 128;
+
+__global__ __launch_bounds__(kSampleBlock) void sample_kernel(WsView w, uint64_t seed, uint64_t stream_base,
+                                                              const uint64_t* __restrict__ counter,
+                                                              int32_t lds_entries, int32_t* __restrict__ m,
+                                                              double* __restrict__ wk) {
+  extern __shared__ double table[];
+  const int32_t b = blockIdx.x;
+  // the stream id is stream_base plus the device step counter when one is given
+  const uint64_t stream_id = stream_base + (counter != nullptr ? counter[0] : 0ull);
   const SysDesc sd = w.sys[b];
-  const int64_t l = g - sd.k_off;
+  if (sd.p == 0) return;
   const double S = w.cdf[sd.cdf_off];
   const double* c = w.cdf + sd.cdf_off + 1;
+  if (sd.cdf_len <= lds_entries) {
+    for (int i = threadIdx.x; i < sd.cdf_len; i += kSampleBlock) table[i] = c[i];
+    __syncthreads();
+    c = table;
+  }
   const int32_t M = (sd.cdf_len - 1) / 2;
   const double Z = c[2 * M];
-  int32_t v[3] = {0, 0, 0};
-  for (int a = 0; a < kMaxAttempts; ++a) {
-    U64x4 ctr = {{(uint64_t)l, (uint64_t)a, 0ull, 0ull}};
-    const U64x4 r = philox4x64_10(ctr, seed + (uint64_t)b, stream_id);
+  for (int32_t l = threadIdx.x; l < sd.p; l += kSampleBlock) {
+    int32_t v[3] = {0, 0, 0};
+    for (int a = 0; a < kMaxAttempts; ++a) {
+      U64x4 ctr = {{(uint64_t)l, (uint64_t)a, 0ull, 0ull}};
+      const U64x4 r = philox4x64_10(ctr, seed + (uint64_t)b, stream_id);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) v[d] = inverse_cdf(c, M, u01_53(r.v[d]) * Z);
-    if (v[0] != 0 || v[1] != 0 || v[2] != 0) break;
+      for (int d = 0; d < 3; ++d) v[d] = inverse_cdf(c, M, u01_53(r.v[d]) * Z);
+      if (v[0] != 0 || v[1] != 0 || v[2] != 0) break;
+    }
+    const int64_t g = sd.k_off + l;
+    m[3 * g] = v[0];
+    m[3 * g + 1] = v[1];
+    m[3 * g + 2] = v[2];
+    wk[g] = (v[0] != 0 || v[1] != 0 || v[2] != 0) ? S / (double)sd.p : 0.0;
   }
-  m[3 * g] = v[0];
-  m[3 * g + 1] = v[1];
-  m[3 * g + 2] = v[2];
-  wk[g] = (v[0] != 0 || v[1] != 0 || v[2] != 0) ? S / (double)sd.p : 0.0;
 }
 
 // ------------------------------------------------------------------ dispatch helpers
+
+// Blocks of a pass: one per work item, or at most `cap` persistent blocks that stride
+// over the items (cap = 0: no cap).
+dim3 grid_for(int32_t n_items, int32_t cap) {
+  return dim3((unsigned)((cap > 0 && cap < n_items) ? cap : n_items));
+}
 
 template <int NPL, int KC, bool CACHE, bool VJP>
 void launch_rho_f32_t(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                       const double* z, const double* q, const int32_t* m, const float* gF,
                       hipStream_t st) {
-  hipLaunchKernelGGL((rho_f32_kernel<NPL, KC, CACHE, VJP>), dim3(s.n_rho_items), dim3(64), 0, st, w,
-                     x, y, z, q, m, gF, s.n_total);
+  hipLaunchKernelGGL((rho_f32_kernel<NPL, KC, CACHE, VJP>), grid_for(s.n_rho_items, s.rho_grid_cap), dim3(64),
+                     0, st, w, x, y, z, q, m, gF, s.n_total, s.n_rho_items);
 }
 
 template <int NPL, int KC, bool VJP>
 void launch_rho_f64_t(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                       const double* z, const double* q, const int32_t* m, const double* gF,
                       hipStream_t st) {
-  hipLaunchKernelGGL((rho_f64_kernel<NPL, KC, VJP>), dim3(s.n_rho_items), dim3(64), 0, st, w, x, y,
-                     z, q, m, gF, s.n_total);
+  hipLaunchKernelGGL((rho_f64_kernel<NPL, KC, VJP>), grid_for(s.n_rho_items, s.rho_grid_cap), dim3(64), 0, st,
+                     w, x, y, z, q, m, gF, s.n_total, s.n_rho_items);
 }
 
 // Particle-tile pass over every (tile, k-range) item; VJP selects adjoint pass B1.
+template <bool CACHE, bool VJP>
+void tile_pass_f32(const LaunchShape& s, const WsView& w, const double* x, const double* y,
+                   const double* z, const double* q, const int32_t* m, const float* g, hipStream_t st) {
+  switch (s.rv.npl * 100 + s.rv.kc) {
+    case 1608: launch_rho_f32_t<16, 8, CACHE, VJP>(s, w, x, y, z, q, m, g, st); break;
+    case 808: launch_rho_f32_t<8, 8, CACHE, VJP>(s, w, x, y, z, q, m, g, st); break;
+    case 1604: launch_rho_f32_t<16, 4, CACHE, VJP>(s, w, x, y, z, q, m, g, st); break;
+    case 3202: launch_rho_f32_t<32, 2, CACHE, VJP>(s, w, x, y, z, q, m, g, st); break;
+    case 1208: launch_rho_f32_t<12, 8, CACHE, VJP>(s, w, x, y, z, q, m, g, st); break;
+    case 2404: launch_rho_f32_t<24, 4, CACHE, VJP>(s, w, x, y, z, q, m, g, st); break;
+    default: break;
+  }
+}
+
 template <bool VJP>
 void launch_tile_pass(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                       const double* z, const double* q, const int32_t* m, const void* gF,
                       hipStream_t st) {
   if (s.precision == RBE_FP32_MIXED) {
     const float* g = static_cast<const float*>(gF);
-    const bool c = s.cached != 0 && !VJP;
-    if (s.rv.npl == 16) {
-      c ? launch_rho_f32_t<16, 8, true, VJP>(s, w, x, y, z, q, m, g, st)
-        : launch_rho_f32_t<16, 8, false, VJP>(s, w, x, y, z, q, m, g, st);
-    } else {
-      c ? launch_rho_f32_t<8, 8, true, VJP>(s, w, x, y, z, q, m, g, st)
-        : launch_rho_f32_t<8, 8, false, VJP>(s, w, x, y, z, q, m, g, st);
+    if constexpr (!VJP) {
+      if (s.cached != 0) {
+        tile_pass_f32<true, false>(s, w, x, y, z, q, m, g, st);
+        return;
+      }
     }
+    tile_pass_f32<false, VJP>(s, w, x, y, z, q, m, g, st);
   } else {
     const double* g = static_cast<const double*>(gF);
-    if (s.rv.npl == 4) launch_rho_f64_t<4, 4, VJP>(s, w, x, y, z, q, m, g, st);
-    else launch_rho_f64_t<8, 4, VJP>(s, w, x, y, z, q, m, g, st);
+    switch (s.rv.npl * 100 + s.rv.kc) {
+      case 804: launch_rho_f64_t<8, 4, VJP>(s, w, x, y, z, q, m, g, st); break;
+      case 404: launch_rho_f64_t<4, 4, VJP>(s, w, x, y, z, q, m, g, st); break;
+      case 408: launch_rho_f64_t<4, 8, VJP>(s, w, x, y, z, q, m, g, st); break;
+      case 802: launch_rho_f64_t<8, 2, VJP>(s, w, x, y, z, q, m, g, st); break;
+      default: break;
+    }
   }
 }
 
@@ -797,22 +956,39 @@ void truncation_rotation(int precision, double* c, double* s) {
   }
 }
 
+template <int NPLF, bool CACHED>
+void force_f32_t(const LaunchShape& s, const WsView& w, const double* x, const double* y, const double* z,
+                 const double* q, const int32_t* m, const double* wk, const double* rho, float* F, double* U,
+                 double rc, double rs, uint64_t* counter, hipStream_t st) {
+  hipLaunchKernelGGL((force_f32_kernel<NPLF, CACHED>), grid_for(s.n_force_items, s.force_grid_cap),
+                     dim3(kForceBlock), 0, st, w, s.n_total, x, y, z, q, m, wk, rho, F, U, rc, rs,
+                     s.n_force_items, counter);
+}
+
+template <int NPLF>
+void force_f64_t(const LaunchShape& s, const WsView& w, const double* x, const double* y, const double* z,
+                 const double* q, const int32_t* m, const double* wk, const double* rho, double* F, double* U,
+                 uint64_t* counter, hipStream_t st) {
+  hipLaunchKernelGGL((force_f64_kernel<NPLF>), grid_for(s.n_force_items, s.force_grid_cap), dim3(kForceBlock),
+                     0, st, w, s.n_total, x, y, z, q, m, wk, rho, F, U, s.n_force_items, counter);
+}
+
 }  // namespace
 
 hipError_t launch_rho(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                       const double* z, const double* q, const int32_t* m, double* rho,
                       hipStream_t st) {
   if (s.n_rho_items > 0) {
+    if (s.ev_rho_begin != nullptr) (void)hipEventRecord(s.ev_rho_begin, st);
     launch_tile_pass<false>(s, w, x, y, z, q, m, nullptr, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (s.ev_rho_end != nullptr) (void)hipEventRecord(s.ev_rho_end, st);
   }
   if (s.p_total > 0) {
     double rc, rs;
     truncation_rotation(s.precision, &rc, &rs);
-    const int per = kReduceBlock / 64;
-    const int64_t blocks = (s.p_total + per - 1) / per;
-    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)blocks), dim3(kReduceBlock), 0, st, w, s.p_total, rho, rc, rs);
+    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)s.p_total), dim3(kReduceBlock), 0, st, w, rho, rc, rs);
     return hipGetLastError();
   }
   return hipSuccess;
@@ -820,37 +996,38 @@ hipError_t launch_rho(const LaunchShape& s, const WsView& w, const double* x, co
 
 hipError_t launch_force(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                         const double* z, const double* q, const int32_t* m, const double* wk,
-                        const double* rho, void* F, double* U, hipStream_t st) {
+                        const double* rho, void* F, double* U, uint64_t* counter, hipStream_t st) {
   if (s.n_force_items == 0) return hipSuccess;
-  const dim3 grid(s.n_force_items), block(kForceBlock);
+  if (s.ev_force_begin != nullptr) (void)hipEventRecord(s.ev_force_begin, st);
   if (s.precision == RBE_FP32_MIXED) {
     double rc, rs;
     truncation_rotation(s.precision, &rc, &rs);
     float* Ff = static_cast<float*>(F);
     if (s.cached) {
       switch (s.fv.nplf) {
-        case 1: hipLaunchKernelGGL((force_f32_kernel<1, true>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, Ff, U, rc, rs); break;
-        case 2: hipLaunchKernelGGL((force_f32_kernel<2, true>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, Ff, U, rc, rs); break;
-        default: hipLaunchKernelGGL((force_f32_kernel<4, true>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, Ff, U, rc, rs); break;
+        case 1: force_f32_t<1, true>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
+        case 2: force_f32_t<2, true>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
+        default: force_f32_t<4, true>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
       }
     } else {
       switch (s.fv.nplf) {
-        case 1: hipLaunchKernelGGL((force_f32_kernel<1, false>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, Ff, U, rc, rs); break;
-        case 2: hipLaunchKernelGGL((force_f32_kernel<2, false>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, Ff, U, rc, rs); break;
-        default: hipLaunchKernelGGL((force_f32_kernel<4, false>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, Ff, U, rc, rs); break;
+        case 1: force_f32_t<1, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
+        case 2: force_f32_t<2, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
+        default: force_f32_t<4, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
       }
     }
   } else {
     double* Fd = static_cast<double*>(F);
     switch (s.fv.nplf) {
-      case 1: hipLaunchKernelGGL((force_f64_kernel<1>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, Fd, U); break;
-      case 2: hipLaunchKernelGGL((force_f64_kernel<2>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, Fd, U); break;
-      default: hipLaunchKernelGGL((force_f64_kernel<4>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, Fd, U); break;
+      case 1: force_f64_t<1>(s, w, x, y, z, q, m, wk, rho, Fd, U, counter, st); break;
+      case 2: force_f64_t<2>(s, w, x, y, z, q, m, wk, rho, Fd, U, counter, st); break;
+      default: force_f64_t<4>(s, w, x, y, z, q, m, wk, rho, Fd, U, counter, st); break;
     }
   }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && s.ev_force_end != nullptr) (void)hipEventRecord(s.ev_force_end, st);
+  return e;
 }
-
 
 hipError_t launch_vjp(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                       const double* z, const double* q, const int32_t* m, const double* wk,
@@ -864,41 +1041,41 @@ hipError_t launch_vjp(const LaunchShape& s, const WsView& w, const double* x, co
     if (e != hipSuccess) return e;
   }
   if (s.p_total > 0) {
-    const int per = kReduceBlock / 64;
-    const int64_t blocks = (s.p_total + per - 1) / per;
-    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)blocks), dim3(kReduceBlock), 0, st, w, s.p_total, w.xy, rc, rs);
+    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)s.p_total), dim3(kReduceBlock), 0, st, w, w.xy, rc, rs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (s.n_force_items == 0) return hipSuccess;
-  const dim3 grid(s.n_force_items), block(kForceBlock);
+  const dim3 grid = grid_for(s.n_force_items, s.force_grid_cap), block(kForceBlock);
+  const int32_t ni = s.n_force_items;
   if (s.precision == RBE_FP32_MIXED) {
     const float* g = static_cast<const float*>(gF);
     float* r = static_cast<float*>(gr);
     float* qq = static_cast<float*>(gq);
     switch (s.fv.nplf) {
-      case 1: hipLaunchKernelGGL((vjp_b2_f32_kernel<1>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, rc, rs); break;
-      case 2: hipLaunchKernelGGL((vjp_b2_f32_kernel<2>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, rc, rs); break;
-      default: hipLaunchKernelGGL((vjp_b2_f32_kernel<4>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, rc, rs); break;
+      case 1: hipLaunchKernelGGL((vjp_b2_f32_kernel<1>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, rc, rs, ni); break;
+      case 2: hipLaunchKernelGGL((vjp_b2_f32_kernel<2>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, rc, rs, ni); break;
+      default: hipLaunchKernelGGL((vjp_b2_f32_kernel<4>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, rc, rs, ni); break;
     }
   } else {
     const double* g = static_cast<const double*>(gF);
     double* r = static_cast<double*>(gr);
     double* qq = static_cast<double*>(gq);
     switch (s.fv.nplf) {
-      case 1: hipLaunchKernelGGL((vjp_b2_f64_kernel<1>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq); break;
-      case 2: hipLaunchKernelGGL((vjp_b2_f64_kernel<2>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq); break;
-      default: hipLaunchKernelGGL((vjp_b2_f64_kernel<4>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq); break;
+      case 1: hipLaunchKernelGGL((vjp_b2_f64_kernel<1>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, ni); break;
+      case 2: hipLaunchKernelGGL((vjp_b2_f64_kernel<2>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, ni); break;
+      default: hipLaunchKernelGGL((vjp_b2_f64_kernel<4>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, ni); break;
     }
   }
   return hipGetLastError();
 }
 
 hipError_t launch_sample(const LaunchShape& s, const WsView& w, uint64_t seed, uint64_t stream_id,
-                         int32_t* m, double* wk, hipStream_t st) {
+                         const uint64_t* counter, int32_t* m, double* wk, hipStream_t st) {
   if (s.p_total == 0) return hipSuccess;
-  const int64_t blocks = (s.p_total + 255) / 256;
-  hipLaunchKernelGGL(sample_kernel, dim3((unsigned)blocks), dim3(256), 0, st, w, s.p_total, seed, stream_id, m, wk);
+  const int32_t entries = std::min<int32_t>(s.max_cdf_len, 8192);
+  hipLaunchKernelGGL(sample_kernel, dim3((unsigned)s.B), dim3(kSampleBlock), sizeof(double) * entries, st, w, seed,
+                     stream_id, counter, entries, m, wk);
   return hipGetLastError();
 }
 

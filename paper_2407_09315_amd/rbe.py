@@ -128,10 +128,13 @@ class Plan:
     """A plan for a batch of systems plus its device workspace (a torch uint8 tensor)."""
 
     def __init__(self, batch: Batch, precision: str = "fp32_mixed", phase_mode: str = "auto",
-                 device=None, tiles=None):
+                 device=None, tiles="auto"):
+        """tiles: (rho_variant, force_variant), "auto" (the tuning cache, else the
+        library defaults) or None (library defaults)."""
         self.lib = load()
         self.batch = batch
         self.precision = precision
+        self.phase_mode = phase_mode
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.n_total = int(batch.sys_off[-1])
         self.p_total = int(batch.k_off[-1])
@@ -140,6 +143,9 @@ class Plan:
         check(self.lib.rbe_plan_create(batch.B, *[_ptr(a) for a in self._arrays], PRECISIONS[precision],
                                        PHASE_MODES[phase_mode], ctypes.byref(handle)), "rbe_plan_create")
         self.handle = handle
+        if isinstance(tiles, str) and tiles == "auto":
+            from .tune import lookup
+            tiles = lookup(precision, phase_mode, batch.B, self.n_total, self.p_total)
         if tiles is not None:
             check(self.lib.rbe_plan_set_tiles(self.handle, int(tiles[0]), int(tiles[1])), "rbe_plan_set_tiles")
         self._alloc()
@@ -155,7 +161,22 @@ class Plan:
 
     def set_tiles(self, rho_variant: int, force_variant: int):
         check(self.lib.rbe_plan_set_tiles(self.handle, rho_variant, force_variant), "rbe_plan_set_tiles")
-        self._alloc()
+        rbe_plan_upload(self.handle, self.ws)
+
+    def tune(self, x, y, z, q, m, w, reps: int = 5, stream=None):
+        """Time every kernel variant on these inputs and keep the fastest (rbe_plan_tune)."""
+        self._check_particles(x, y, z, q)
+        self._check_k(m, w)
+        rho = torch.empty((self.p_total, 2), dtype=torch.float64, device=self.device)
+        F = torch.empty((3, self.n_total), dtype=self.force_dtype, device=self.device)
+        U = torch.empty(self.batch.B, dtype=torch.float64, device=self.device)
+        rv, fv = ctypes.c_int32(), ctypes.c_int32()
+        rms, fms = ctypes.c_double(), ctypes.c_double()
+        check(self.lib.rbe_plan_tune(self.handle, _ptr(x), _ptr(y), _ptr(z), _ptr(q), _ptr(m), _ptr(w),
+                                     _ptr(rho), _ptr(F), _ptr(U), _ptr(self.ws), _stream(stream), reps,
+                                     ctypes.byref(rv), ctypes.byref(fv), ctypes.byref(rms), ctypes.byref(fms)),
+              "rbe_plan_tune")
+        return {"rho_variant": rv.value, "force_variant": fv.value, "rho_ms": rms.value, "force_ms": fms.value}
 
     def tiles(self):
         a, b = ctypes.c_int32(), ctypes.c_int32()
@@ -228,6 +249,19 @@ class Plan:
         rbe_kspace_vjp(self.handle, x, y, z, q, m, w, rho, gU, gF, gr, gq, self.ws, stream)
         return gr, gq
 
+    def set_timing_events(self, rho_begin=None, rho_end=None, force_begin=None, force_end=None):
+        """Record torch.cuda.Events (already recorded once, so their handles exist) around the kernels."""
+        h = [ctypes.c_void_p(e.cuda_event) if e is not None else ctypes.c_void_p(0)
+             for e in (rho_begin, rho_end, force_begin, force_end)]
+        check(self.lib.rbe_plan_set_timing_events(self.handle, *h), "rbe_plan_set_timing_events")
+
+    def set_grid_caps(self, rho_cap: int, force_cap: int):
+        check(self.lib.rbe_plan_set_grid_caps(self.handle, rho_cap, force_cap), "rbe_plan_set_grid_caps")
+
+    def graph(self, x, y, z, q, seed: int, stream_base: int = 0, step_counter=None):
+        """A captured evaluation (sample -> rho -> force) of this plan; see EvalGraph."""
+        return EvalGraph(self, x, y, z, q, seed, stream_base, step_counter)
+
     def sample_k_device(self, seed: int, stream_id: int, m=None, w=None, stream=None):
         if m is None:
             m = torch.empty((self.p_total, 3), dtype=torch.int32, device=self.device)
@@ -235,3 +269,39 @@ class Plan:
             w = torch.empty(self.p_total, dtype=torch.float64, device=self.device)
         rbe_sample_k_device(self.handle, seed, stream_id, m, w, self.ws, stream)
         return m, w
+
+
+class EvalGraph:
+    """One RBE evaluation captured into a HIP graph (rbe_graph_create / rbe_graph_launch).
+
+    Owns its output buffers: m, w, rho, F, U.  With a step counter (a one-element
+    uint64 device tensor) every replay draws new wave vectors.
+    """
+
+    def __init__(self, plan: Plan, x, y, z, q, seed, stream_base=0, step_counter=None):
+        plan._check_particles(x, y, z, q)
+        self.plan = plan
+        dev = plan.device
+        self.inputs = (x, y, z, q)
+        self.m = torch.zeros((plan.p_total, 3), dtype=torch.int32, device=dev)
+        self.w = torch.zeros(plan.p_total, dtype=torch.float64, device=dev)
+        self.rho = torch.zeros((plan.p_total, 2), dtype=torch.float64, device=dev)
+        self.F = torch.zeros((3, plan.n_total), dtype=plan.force_dtype, device=dev)
+        self.U = torch.zeros(plan.batch.B, dtype=torch.float64, device=dev)
+        self.counter = step_counter
+        torch.cuda.synchronize()
+        handle = ctypes.c_void_p()
+        check(plan.lib.rbe_graph_create(plan.handle, seed, stream_base, _ptr(step_counter), _ptr(x), _ptr(y),
+                                        _ptr(z), _ptr(q), _ptr(self.m), _ptr(self.w), _ptr(self.rho),
+                                        _ptr(self.F), _ptr(self.U), _ptr(plan.ws), ctypes.byref(handle)),
+              "rbe_graph_create")
+        self.handle = handle
+
+    def launch(self, stream=None):
+        check(self.plan.lib.rbe_graph_launch(self.handle, _stream(stream)), "rbe_graph_launch")
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.plan.lib.rbe_graph_destroy(h)
+            self.handle = None

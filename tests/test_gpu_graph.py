@@ -1,0 +1,57 @@
+"""GPU checks of the captured evaluation graph and persistent grids.
+
+  * every replay of rbe_graph equals the eager calls with the same wave vectors,
+    bit for bit, with eager work and synchronisations between the replays, and
+    the device step counter advances once per replay;
+  * capped (persistent) grids give bitwise the results of one block per item.
+"""
+import numpy as np
+import pytest
+import torch
+
+import rbe_inputs as ri
+from paper_2407_09315_amd import Batch, Plan, rbe_sample_k
+from parity_util import note, particles, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_graph_replays_match_eager(precision):
+    reps = ri.c5_replicas(B=4)
+    systems = reps.systems
+    batch = Batch.from_sizes([s.n for s in systems], [100] * 4, [s.L for s in systems], reps.alphas)
+    plan = Plan(batch, precision=precision)
+    cat = [to_dev(np.concatenate([getattr(s, a) for s in systems])) for a in ("x", "y", "z", "q")]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        counter = torch.zeros(1, dtype=torch.int64, device=cat[0].device)
+        g = plan.graph(*cat, seed=900, stream_base=5, step_counter=counter)
+        for r in range(3):
+            g.launch()
+            torch.cuda.synchronize()
+            note(f"replay {r} {precision}")
+            # eager evaluation with the same wave vectors, run between replays
+            m, w = plan.sample_k_device(900, 5 + r)
+            F, U, rho = plan.forward(*cat, m, w)
+            torch.cuda.synchronize()
+            assert torch.equal(g.m, m) and torch.equal(g.w, w)
+            assert torch.equal(g.rho, rho) and torch.equal(g.F, F) and torch.equal(g.U, U)
+            mh, _, _ = rbe_sample_k(900 + 1, 5 + r, systems[1].L, reps.alphas[1], 100)
+            assert np.array_equal(g.m[100:200].cpu().numpy(), mh)
+            assert int(counter.item()) == r + 1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_persistent_grid_caps_bitwise(precision):
+    s, alpha, P = ri.c4_differentiable()
+    m, w, _ = rbe_sample_k(5, 0, s.L, alpha, P)
+    X = particles(s)
+    mt, wt = to_dev(m, torch.int32), to_dev(w)
+    plan = Plan(Batch.single(s.n, P, s.L, alpha), precision=precision)
+    F0, U0, r0 = plan.forward(*X, mt, wt)
+    for caps in [(37, 5), (1024, 256), (1, 1)]:
+        plan.set_grid_caps(*caps)
+        F1, U1, r1 = plan.forward(*X, mt, wt)
+        torch.cuda.synchronize()
+        assert torch.equal(F0, F1) and torch.equal(U0, U1) and torch.equal(r0, r1), caps

@@ -61,11 +61,17 @@ def test_small_parity(case, precision):
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 1023, 1025, 5000])
 def test_ragged_sizes(n, precision):
     s = ri.random_charges(n, 9.0, 40 + n)
-    if n == 1:
-        s.q[:] = 1.3     # a lone charge (non-neutral input is computed literally)
     # positions partly outside the box: results are periodic in each coordinate
     s.x[::3] += 2 * s.L
     s.y[1::4] -= 3 * s.L
+    if n == 1:
+        # a lone charge feels no force from its own periodic images; its energy is q^2 sum c/2
+        s.q[:] = 1.3
+        m, w, _ = rbe_sample_k(18, 0, s.L, 0.3, 7)
+        F, U, _ = _run(s, 0.3, m, w, precision)
+        _, U_ref, _ = oracle.force_energy(s.x, s.y, s.z, s.q, m, w, s.L)
+        assert rel(U, U_ref) < TOL[precision] and np.max(np.abs(F)) < TOL[precision] * U_ref
+        return
     for P in (1, 7, 100):
         _check(f"ragged n={n}", s, 0.3, P, 17 + P, precision)
 
