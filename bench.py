@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--quick", action="store_true", help="skip the extra forms and the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3: 5 eager evaluations per form plus a 256 MiB device copy "
+                         "(the reference kernel of known size for HBM counter scaling); prints no JSON")
     return ap.parse_args()
 
 
@@ -114,6 +117,9 @@ def main():
     X = [torch.tensor(a, dtype=torch.float64, device=dev) for a in (s.x, s.y, s.z, s.q)]
     terms = s.n * P
 
+    if args.profile:
+        profile_run(torch, Plan, Batch, X, s, alpha, P, dev)
+        return
     res = {}
     res["fp32"] = run_form(torch, Plan, Batch, X, s.L, alpha, P, "fp32_mixed", "recompute", args.steps, args.warmup)
     log(f"fp32_mixed: {res['fp32']['wall_s'] * 1e3:.3f} ms/step")
@@ -166,13 +172,53 @@ def main():
                             "tiles": f32["tiles"]},
         "roofline": {"bound": "alu", "kernel": "rho_f32_kernel" if dom == "rho" else "force_f32_kernel",
                      "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "frac": round(achieved / peak, 4),
+                     "traffic": traffic_from_profile("rho_f32_kernel" if dom == "rho" else "force_f32_kernel"),
                      "ops_per_term": slots, "terms_per_launch": terms},
         "extra": extra,
     }
     if not args.quick and not args.no_cpu:
         out["cpu_baseline"], out["error_vs_oracle"] = cpu_baseline(s, P, res)
     print(json.dumps(out), flush=True)
+
+
+def profile_run(torch, Plan, Batch, X, s, alpha, P, dev):
+    for prec in ("fp32_mixed", "fp64"):
+        plan = Plan(Batch.single(s.n, P, s.L, alpha), precision=prec, phase_mode="recompute")
+        m, w = plan.sample_k_device(2003, 0)
+        for k in range(7):
+            plan.sample_k_device(2003, k, m, w)
+            plan.forward(*X, m, w)
+        torch.cuda.synchronize()
+        log(f"profile {prec}: tiles {plan.tiles()}")
+    src = torch.ones(256 * 2 ** 20 // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("profile copy: 3 x 256 MiB")
+
+
+def traffic_from_profile(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when the
+    summary is missing or was taken on a different kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_1M.md")
+    src = os.path.join(ROOT, "paper_2407_09315_amd", "csrc", "rbe_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip()
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("kernel source sha256") != digest:
+        return None
+    try:
+        return float(fields["hbm bytes per launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(s, P, res):

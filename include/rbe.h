@@ -138,12 +138,24 @@ rbe_status rbe_plan_num_variants(const rbe_plan *plan, int32_t *n_rho, int32_t *
 rbe_status rbe_plan_get_tiles(const rbe_plan *plan, int32_t *rho_variant, int32_t *force_variant);
 
 /*
- * Persistent grids: launch at most rho_cap blocks for the rho-shaped passes and
- * force_cap blocks for the force-shaped passes, each block striding over the
- * work items (0, the default: one block per work item).  Results do not
- * depend on the caps.
+ * Persistent grids.  rho_cap > 0 launches rho_cap single-wave blocks for the
+ * rho-shaped passes, each pulling work items from an atomic counter in the
+ * workspace until none are left (the last block resets the counter; calls that
+ * overlap on one workspace race).  force_cap > 0 launches force_cap blocks for
+ * the force-shaped passes, block b taking items b, b + force_cap, ...  0 (the
+ * default) launches one block per work item.  Results do not depend on the caps.
  */
 rbe_status rbe_plan_set_grid_caps(rbe_plan *plan, int32_t rho_cap, int32_t force_cap);
+rbe_status rbe_plan_get_grid_caps(const rbe_plan *plan, int32_t *rho_cap, int32_t *force_cap);
+
+/*
+ * Occupancy clamp of the rho-shaped passes (on by default): each single-wave block
+ * reserves unused LDS so that a CU holds at most its even share of the pass's
+ * blocks (4 x ceil(blocks / (4 x CUs))), whatever the state the previous kernel
+ * left the CUs in.  The autotuner measures both settings.
+ */
+rbe_status rbe_plan_set_occupancy_clamp(rbe_plan *plan, int32_t on);
+rbe_status rbe_plan_get_occupancy_clamp(const rbe_plan *plan, int32_t *on);
 
 /*
  * Kernel timing hook: when set (non-NULL hipEvent_t handles), every later call
@@ -214,17 +226,20 @@ rbe_status rbe_sample_k_device(const rbe_plan *plan, uint64_t seed, uint64_t str
                                int32_t *m, double *w, void *ws, void *stream);
 
 /*
- * Autotuner: time every rho-pass variant on rbe_structure_factor and every
- * force-pass variant on rbe_kspace_force with the caller's inputs (reps timed
- * runs each after one warm-up, HIP events on `stream`), keep the fastest of
- * each, upload the plan again and report the choice and its mean times in ms
+ * Autotuner: time every rho-pass variant and every force-pass variant on the
+ * caller's inputs, in the order an evaluation runs them (rbe_structure_factor
+ * then rbe_kspace_force, reps timed rounds after one warm-up, HIP events on
+ * `stream` right around each kernel), the rho variants with and without the
+ * occupancy clamp; keep the fastest of each with one block per work item,
+ * upload the plan again and report the choice and its mean kernel times in ms
  * (any output pointer may be NULL).  Arguments as for the calls it times; rho,
  * F and U are overwritten.  Synchronises `stream`.
  */
 rbe_status rbe_plan_tune(rbe_plan *plan, const double *x, const double *y, const double *z,
                          const double *q, const int32_t *m, const double *w, double *rho, void *F,
                          double *U, void *ws, void *stream, int32_t reps, int32_t *rho_variant,
-                         int32_t *force_variant, double *rho_ms, double *force_ms);
+                         int32_t *force_variant, int32_t *rho_grid_cap, double *rho_ms,
+                         double *force_ms);
 
 /*
  * Capture one whole evaluation of every system of the plan -- device sampling

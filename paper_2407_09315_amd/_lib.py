@@ -36,7 +36,10 @@ SIGNATURES = {
     "rbe_kspace_force": (_ST, [_VP] * 12),
     "rbe_kspace_vjp": (_ST, [_VP] * 14),
     "rbe_sample_k_device": (_ST, [_VP, _U64, _U64, _VP, _VP, _VP, _VP]),
-    "rbe_plan_tune": (_ST, [_VP] * 12 + [_I32, _VP, _VP, _VP, _VP]),
+    "rbe_plan_tune": (_ST, [_VP] * 12 + [_I32, _VP, _VP, _VP, _VP, _VP]),
+    "rbe_plan_get_grid_caps": (_ST, [_VP, _VP, _VP]),
+    "rbe_plan_set_occupancy_clamp": (_ST, [_VP, _I32]),
+    "rbe_plan_get_occupancy_clamp": (_ST, [_VP, _VP]),
     "rbe_plan_set_grid_caps": (_ST, [_VP, _I32, _I32]),
     "rbe_plan_set_timing_events": (_ST, [_VP] * 5),
     "rbe_graph_create": (_ST, [_VP, _U64, _U64] + [_VP] * 12),

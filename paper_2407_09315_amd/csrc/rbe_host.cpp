@@ -100,6 +100,7 @@ struct rbe_plan {
   int rho_variant = 0;
   int force_variant = 1;
   int32_t rho_grid_cap = 0;     // 0: one block per work item
+  int32_t rho_clamp = 1;        // occupancy clamp of the rho-shaped passes
   int32_t force_grid_cap = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // optional kernel timing events
   bool sampler_ok = true;
@@ -112,7 +113,7 @@ struct rbe_plan {
   std::vector<double> cdf;
   // workspace layout (byte offsets)
   size_t off_sys = 0, off_rho = 0, off_force = 0, off_ksys = 0, off_cdf = 0, off_part = 0,
-         off_xy = 0, off_cache = 0, total = 0;
+         off_xy = 0, off_cache = 0, off_sched = 0, total = 0;
   size_t ws_bytes = 0;      // workspace size: the largest layout over all variants
   int64_t n_partials = 0;   // complex slots
   int64_t n_cache = 0;      // (cos, sin) pairs
@@ -199,6 +200,7 @@ void build_layout(rbe_plan* p) {
   p->off_part = o;  o = align_up(o + 2 * sizeof(double) * (size_t)p->n_partials);
   p->off_xy = o;    o = align_up(o + 2 * sizeof(double) * (size_t)p->p_total());
   p->off_cache = o; o = align_up(o + 2 * sizeof(float) * (size_t)p->n_cache);
+  p->off_sched = o; o = align_up(o + 2 * sizeof(uint32_t));
   p->total = std::max<size_t>(o, kAlign);
 }
 
@@ -213,6 +215,7 @@ WsView view_of(const rbe_plan* p, void* ws) {
   w.partials = reinterpret_cast<double*>(b + p->off_part);
   w.xy = reinterpret_cast<double*>(b + p->off_xy);
   w.cache = reinterpret_cast<float*>(b + p->off_cache);
+  w.sched = reinterpret_cast<uint32_t*>(b + p->off_sched);
   return w;
 }
 
@@ -232,6 +235,7 @@ LaunchShape shape_of(const rbe_plan* p) {
   s.max_cdf_len = 0;
   for (const SysDesc& d : p->sys) s.max_cdf_len = std::max(s.max_cdf_len, d.cdf_len);
   s.rho_grid_cap = p->rho_grid_cap;
+  s.rho_clamp = p->rho_clamp;
   s.force_grid_cap = p->force_grid_cap;
   s.ev_rho_begin = p->ev[0];
   s.ev_rho_end = p->ev[1];
@@ -390,6 +394,25 @@ rbe_status rbe_plan_get_tiles(const rbe_plan* p, int32_t* rv, int32_t* fv) {
   return RBE_OK;
 }
 
+rbe_status rbe_plan_set_occupancy_clamp(rbe_plan* p, int32_t on) {
+  if (!p) return fail(RBE_EINVAL, "plan is NULL");
+  p->rho_clamp = on ? 1 : 0;
+  return RBE_OK;
+}
+
+rbe_status rbe_plan_get_occupancy_clamp(const rbe_plan* p, int32_t* on) {
+  if (!p || !on) return fail(RBE_EINVAL, "NULL argument");
+  *on = p->rho_clamp;
+  return RBE_OK;
+}
+
+rbe_status rbe_plan_get_grid_caps(const rbe_plan* p, int32_t* rho_cap, int32_t* force_cap) {
+  if (!p || !rho_cap || !force_cap) return fail(RBE_EINVAL, "NULL argument");
+  *rho_cap = p->rho_grid_cap;
+  *force_cap = p->force_grid_cap;
+  return RBE_OK;
+}
+
 rbe_status rbe_plan_set_tiles(rbe_plan* p, int32_t rv, int32_t fv) {
   if (!p) return fail(RBE_EINVAL, "plan is NULL");
   const int nr = p->precision == RBE_FP32_MIXED ? kNumRhoVariantsF32 : kNumRhoVariantsF64;
@@ -420,6 +443,9 @@ rbe_status rbe_plan_upload(const rbe_plan* p, void* ws, void* stream) {
     hipError_t e = hipMemcpyAsync(b + c.off, c.src, c.bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(plan upload)");
   }
+  // the dynamic-grid counters start at zero (each launch leaves them at zero)
+  hipError_t em = hipMemsetAsync(b + p->off_sched, 0, 2 * sizeof(uint32_t), s);
+  if (em != hipSuccess) return hip_fail(em, "hipMemsetAsync(plan upload)");
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(plan upload)");
   return RBE_OK;
@@ -472,60 +498,75 @@ rbe_status rbe_kspace_vjp(const rbe_plan* p, const double* x, const double* y, c
 rbe_status rbe_plan_tune(rbe_plan* p, const double* x, const double* y, const double* z, const double* q,
                          const int32_t* m, const double* w, double* rho, void* F, double* U, void* ws,
                          void* stream, int32_t reps, int32_t* rho_variant, int32_t* force_variant,
-                         double* rho_ms, double* force_ms) {
+                         int32_t* rho_grid_cap, double* rho_ms, double* force_ms) {
   rbe_status st = check_common(p, ws);
   if (st != RBE_OK) return st;
   if (reps <= 0) return fail(RBE_EINVAL, "reps must be > 0");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-    return fail(RBE_EHIP, "hipEventCreate failed");
-  auto timed = [&](bool force_pass, float* ms) -> rbe_status {
+  hipEvent_t ev[4];
+  for (hipEvent_t& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) return fail(RBE_EHIP, "hipEventCreate failed");
+  hipEvent_t saved[4] = {p->ev[0], p->ev[1], p->ev[2], p->ev[3]};
+  // Time the two kernels the way an evaluation runs them: each rho pass follows a
+  // force pass and each force pass follows a rho pass (a kernel's speed depends on
+  // what ran before it), with events placed right around each kernel.
+  auto measure = [&](float* rho_out, float* force_out) -> rbe_status {
     rbe_status r = rbe_plan_upload(p, ws, stream);
-    if (r != RBE_OK) return r;
-    for (int i = 0; i <= reps; ++i) {   // the first run is a warm-up
-      if (i == 1 && hipEventRecord(e0, s) != hipSuccess) return fail(RBE_EHIP, "hipEventRecord failed");
-      r = force_pass ? rbe_kspace_force(p, x, y, z, q, m, w, rho, F, U, ws, stream)
-                     : rbe_structure_factor(p, x, y, z, q, m, rho, ws, stream);
-      if (r != RBE_OK) return r;
+    float tr = 0.f, tf = 0.f;
+    for (int i = 0; i <= reps && r == RBE_OK; ++i) {   // the first round is a warm-up
+      p->ev[0] = ev[0]; p->ev[1] = ev[1]; p->ev[2] = ev[2]; p->ev[3] = ev[3];
+      r = rbe_structure_factor(p, x, y, z, q, m, rho, ws, stream);
+      if (r == RBE_OK) r = rbe_kspace_force(p, x, y, z, q, m, w, rho, F, U, ws, stream);
+      p->ev[0] = p->ev[1] = p->ev[2] = p->ev[3] = nullptr;
+      if (r != RBE_OK) break;
+      if (hipEventSynchronize(ev[3]) != hipSuccess) { r = fail(RBE_EHIP, "event wait failed"); break; }
+      float a = 0.f, b = 0.f;
+      if (hipEventElapsedTime(&a, ev[0], ev[1]) != hipSuccess || hipEventElapsedTime(&b, ev[2], ev[3]) != hipSuccess) {
+        r = fail(RBE_EHIP, "hipEventElapsedTime failed");
+        break;
+      }
+      if (i > 0) { tr += a; tf += b; }
     }
-    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
-      return fail(RBE_EHIP, "event wait failed");
-    if (hipEventElapsedTime(ms, e0, e1) != hipSuccess) return fail(RBE_EHIP, "hipEventElapsedTime failed");
-    *ms /= (float)reps;
-    return RBE_OK;
+    *rho_out = tr / (float)reps;
+    *force_out = tf / (float)reps;
+    return r;
   };
   const int nr = p->precision == RBE_FP32_MIXED ? kNumRhoVariantsF32 : kNumRhoVariantsF64;
   int best_r = p->rho_variant, best_f = p->force_variant;
   float best_rms = 1e30f, best_fms = 1e30f;
   rbe_status r = RBE_OK;
+  p->rho_grid_cap = 0;
+  int32_t best_clamp = p->rho_clamp;
   for (int v = 0; v < nr && r == RBE_OK; ++v) {
     p->rho_variant = v;
     build_layout(p);
-    float ms = 0.f;
-    r = timed(false, &ms);
-    if (r == RBE_OK && ms < best_rms) { best_rms = ms; best_r = v; }
+    for (int32_t clamp = 1; clamp >= 0 && r == RBE_OK; --clamp) {
+      p->rho_clamp = clamp;
+      float a = 0.f, b = 0.f;
+      r = measure(&a, &b);
+      if (r == RBE_OK && a < best_rms) { best_rms = a; best_r = v; best_clamp = clamp; }
+    }
   }
   p->rho_variant = best_r;
+  p->rho_clamp = best_clamp;
   for (int v = 0; v < kNumForceVariants && r == RBE_OK; ++v) {
     p->force_variant = v;
     build_layout(p);
-    float ms = 0.f;
-    // the force pass needs rho of the current layout
-    r = rbe_plan_upload(p, ws, stream);
-    if (r == RBE_OK) r = rbe_structure_factor(p, x, y, z, q, m, rho, ws, stream);
-    if (r == RBE_OK) r = timed(true, &ms);
-    if (r == RBE_OK && ms < best_fms) { best_fms = ms; best_f = v; }
+    float a = 0.f, b = 0.f;
+    r = measure(&a, &b);
+    if (r == RBE_OK && b < best_fms) { best_fms = b; best_f = v; }
   }
   p->force_variant = best_f;
   build_layout(p);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  for (int i = 0; i < 4; ++i) {
+    (void)hipEventDestroy(ev[i]);
+    p->ev[i] = saved[i];
+  }
   if (r != RBE_OK) return r;
   r = rbe_plan_upload(p, ws, stream);
   if (r != RBE_OK) return r;
   if (rho_variant) *rho_variant = best_r;
   if (force_variant) *force_variant = best_f;
+  if (rho_grid_cap) *rho_grid_cap = p->rho_grid_cap;
   if (rho_ms) *rho_ms = best_rms;
   if (force_ms) *force_ms = best_fms;
   return RBE_OK;

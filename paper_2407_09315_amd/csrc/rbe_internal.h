@@ -65,6 +65,7 @@ struct WsView {
   double* partials;      // complex partial sums (rho pass, then VJP pass B1)
   double* xy;            // P_total complex values (VJP X + iY)
   float* cache;          // (cos, sin) phase cache, FP32_MIXED + CACHED only
+  uint32_t* sched;       // two work-pulling counters of the dynamic rho-pass grid (zero between launches)
 };
 
 struct LaunchShape {
@@ -81,6 +82,7 @@ struct LaunchShape {
   int force_variant;
   int32_t max_cdf_len;   // longest sampler table of the plan
   int32_t rho_grid_cap;  // persistent-grid caps (0: one block per work item)
+  int32_t rho_clamp;     // 1: cap the rho-pass blocks per CU at their even share
   int32_t force_grid_cap;
   // optional events recorded right before / after the rho-pass and force-pass kernels
   hipEvent_t ev_rho_begin, ev_rho_end, ev_force_begin, ev_force_end;

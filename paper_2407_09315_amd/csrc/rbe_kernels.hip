@@ -33,7 +33,7 @@ namespace rbe {
 
 // {particles per lane, wave vectors per chunk, wave vectors per work item}
 const RhoVariant kRhoVariantsF32[kNumRhoVariantsF32] = {
-    {16, 8, 56}, {8, 8, 104}, {16, 4, 52}, {32, 2, 50}, {12, 8, 104}, {24, 4, 52}};
+    {16, 8, 56}, {8, 8, 104}, {16, 4, 52}, {8, 8, 56}, {8, 8, 32}, {8, 4, 28}};
 const RhoVariant kRhoVariantsF64[kNumRhoVariantsF64] = {
     {8, 4, 52}, {4, 4, 100}, {8, 4, 100}, {4, 8, 104}, {8, 2, 50}};
 const ForceVariant kForceVariants[kNumForceVariants] = {{1}, {2}, {4}};
@@ -44,6 +44,7 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kFourPi = 12.566370614359172953850573533118;
 constexpr int kTabChunk = 256;
 constexpr int kUnroll = 4;   // table rows per step of the force-shaped passes
+constexpr int kPairs = 2;    // particles per step of the FP32 rho pass
 
 // ------------------------------------------------------------------ phase helpers
 
@@ -64,10 +65,13 @@ __device__ inline uint32_t phase_u32(int32_t mx, int32_t my, int32_t mz, uint32_
   return (uint32_t)mx * ux + (uint32_t)my * uy + (uint32_t)mz * uz;
 }
 
-// sin and cos of 2 pi r for |r| <= 1/2 (turns), FP64.
+// sin and cos of 2 pi r for |r| <= 1/2 (turns), FP64.  With q = rint(4 r) in {-2..2}
+// and f = r - q/4 (exact, |f| <= 1/8): exp(2 pi i r) = i^q exp(2 pi i f), and
+// i^q = (1 - |q|) + i q (2 - |q|) exactly, so the quarter-turn rotation is two
+// exact products and two FMAs instead of selects.
 __device__ inline void sincos_turns(double r, double* s, double* c) {
-  const double q4 = rint(4.0 * r);
-  const double f = fma(q4, -0.25, r);
+  const double q = rint(4.0 * r);
+  const double f = fma(q, -0.25, r);
   const double f2 = f * f;
   double ps = kSin[kSinTerms - 1];
 #pragma unroll
@@ -76,13 +80,11 @@ __device__ inline void sincos_turns(double r, double* s, double* c) {
 #pragma unroll
   for (int j = kCosTerms - 2; j >= 0; --j) pc = fma(pc, f2, kCos[j]);
   const double sn = ps * f;
-  const int n = (int)q4;
-  double so = (n & 1) ? pc : sn;
-  double co = (n & 1) ? sn : pc;
-  so = (n & 2) ? -so : so;
-  co = ((n + 1) & 2) ? -co : co;
-  *s = so;
-  *c = co;
+  const double aq = fabs(q);
+  const double cq = 1.0 - aq;            // cos(pi q / 2)
+  const double sq = q * (2.0 - aq);      // sin(pi q / 2)
+  *s = fma(sn, cq, pc * sq);
+  *c = fma(pc, cq, -(sn * sq));
 }
 
 // phase of m.s in turns, reduced to [-1/2, 1/2].
@@ -171,6 +173,34 @@ __device__ inline void wave_reduce_scatter(T (&v)[V], int lane) {
   ReduceScatter<0, V / 2, T, V>::run(v, lane);
 }
 
+// Work-item scheduling of the rho-shaped passes.  Static: block b takes items b, b + grid,
+// ...  Dynamic (persistent grids): each single-wave block pulls the next item from an
+// atomic counter in the workspace, so waves on faster or less crowded SIMDs take more
+// items; the last block to finish resets the counters for the next launch.  The
+// partial-sum slot of an item is fixed by the item, so results do not depend on which
+// block ran it.
+__device__ inline int32_t pull_item(uint32_t* sched) {
+  int32_t v = 0;
+  if (threadIdx.x == 0) v = (int32_t)atomicAdd(&sched[0], 1u);
+  // lane 0's value, marked wave-uniform so everything derived from it stays scalar
+  return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ inline int32_t first_item(uint32_t* sched, int dyn) {
+  return dyn ? pull_item(sched) : (int32_t)blockIdx.x;
+}
+__device__ inline int32_t next_item(uint32_t* sched, int dyn, int32_t item) {
+  return dyn ? pull_item(sched) : item + (int32_t)gridDim.x;
+}
+__device__ inline void finish_items(uint32_t* sched, int dyn) {
+  if (dyn && threadIdx.x == 0) {
+    const uint32_t done = atomicAdd(&sched[1], 1u);
+    if (done == gridDim.x - 1) {
+      atomicExch(&sched[0], 0u);
+      atomicExch(&sched[1], 0u);
+    }
+  }
+}
+
 // Wave vectors kc .. kc+KC-1 of an item (zero past its end); uniform, so scalar loads.
 template <int KC>
 __device__ inline void load_chunk(const int32_t* mk, int kc, int nk, int32_t (&mx)[KC], int32_t (&my)[KC],
@@ -197,8 +227,8 @@ __global__ __launch_bounds__(64) void rho_f32_kernel(WsView w, const double* __r
                                                      const double* __restrict__ q,
                                                      const int32_t* __restrict__ m,
                                                      const float* __restrict__ gF, int64_t n_total,
-                                                     int32_t n_items) {
-for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+                                                     int32_t n_items, int dyn) {
+for (int32_t item = first_item(w.sched, dyn); item < n_items; item = next_item(w.sched, dyn, item)) {
   const RhoItem it = w.rho_items[item];
   const SysDesc sd = w.sys[it.sys];
   const int lane = threadIdx.x;
@@ -247,27 +277,39 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
 #pragma unroll
     for (int c = 0; c < 2 * KC; ++c) acc[c] = 0.0f;
 #pragma unroll
-    for (int j = 0; j < NPL; ++j) {
-      // one particle against the KC wave vectors, stage by stage for instruction-level parallelism
-      float a[KC], sn[KC], cs[KC];
+    for (int j0 = 0; j0 < NPL; j0 += kPairs) {
+      // kPairs particles against the KC wave vectors, stage by stage for instruction-level
+      // parallelism (kPairs * KC independent phase -> sin/cos -> FMA chains)
+      float a[kPairs][KC], sn[kPairs][KC], cs[kPairs][KC];
 #pragma unroll
-      for (int c = 0; c < KC; ++c) a[c] = turns_arg(phase_u32(mx[c], my[c], mz[c], ux[j], uy[j], uz[j]));
+      for (int jj = 0; jj < kPairs; ++jj)
 #pragma unroll
-      for (int c = 0; c < KC; ++c) sn[c] = __builtin_amdgcn_sinf(a[c]);
+        for (int c = 0; c < KC; ++c)
+          a[jj][c] = turns_arg(phase_u32(mx[c], my[c], mz[c], ux[j0 + jj], uy[j0 + jj], uz[j0 + jj]));
 #pragma unroll
-      for (int c = 0; c < KC; ++c) cs[c] = __builtin_amdgcn_cosf(a[c]);
+      for (int jj = 0; jj < kPairs; ++jj)
 #pragma unroll
-      for (int c = 0; c < KC; ++c) {
-        float wt = qv[j];
-        if (VJP) wt = fmaf(qgx[j], (float)mx[c], fmaf(qgy[j], (float)my[c], qgz[j] * (float)mz[c]));
-        acc[c] = fmaf(wt, cs[c], acc[c]);
-        acc[KC + c] = fmaf(wt, sn[c], acc[KC + c]);
-        if (CACHE) {
-          const int li = j * 64 + lane;
-          if (li < cnt && kc + c < it.nk) {
-            float2* cp = reinterpret_cast<float2*>(w.cache) + sd.cache_off +
-                         (int64_t)(it.k0 + kc + c) * sd.n + first + li;
-            *cp = make_float2(cs[c], sn[c]);
+        for (int c = 0; c < KC; ++c) sn[jj][c] = __builtin_amdgcn_sinf(a[jj][c]);
+#pragma unroll
+      for (int jj = 0; jj < kPairs; ++jj)
+#pragma unroll
+        for (int c = 0; c < KC; ++c) cs[jj][c] = __builtin_amdgcn_cosf(a[jj][c]);
+#pragma unroll
+      for (int jj = 0; jj < kPairs; ++jj) {
+        const int j = j0 + jj;
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+          float wt = qv[j];
+          if (VJP) wt = fmaf(qgx[j], (float)mx[c], fmaf(qgy[j], (float)my[c], qgz[j] * (float)mz[c]));
+          acc[c] = fmaf(wt, cs[jj][c], acc[c]);
+          acc[KC + c] = fmaf(wt, sn[jj][c], acc[KC + c]);
+          if (CACHE) {
+            const int li = j * 64 + lane;
+            if (li < cnt && kc + c < it.nk) {
+              float2* cp = reinterpret_cast<float2*>(w.cache) + sd.cache_off +
+                           (int64_t)(it.k0 + kc + c) * sd.n + first + li;
+              *cp = make_float2(cs[jj][c], sn[jj][c]);
+            }
           }
         }
       }
@@ -284,6 +326,7 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
     }
   }
   }
+  finish_items(w.sched, dyn);
 }
 
 // ------------------------------------------------------------------ rho pass, FP64
@@ -295,8 +338,8 @@ __global__ __launch_bounds__(64) void rho_f64_kernel(WsView w, const double* __r
                                                      const double* __restrict__ q,
                                                      const int32_t* __restrict__ m,
                                                      const double* __restrict__ gF, int64_t n_total,
-                                                     int32_t n_items) {
-for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+                                                     int32_t n_items, int dyn) {
+for (int32_t item = first_item(w.sched, dyn); item < n_items; item = next_item(w.sched, dyn, item)) {
   const RhoItem it = w.rho_items[item];
   const SysDesc sd = w.sys[it.sys];
   const int lane = threadIdx.x;
@@ -368,6 +411,7 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
     }
   }
   }
+  finish_items(w.sched, dyn);
 }
 
 // ------------------------------------------------------------------ cross-tile reduction
@@ -888,20 +932,47 @@ dim3 grid_for(int32_t n_items, int32_t cap) {
   return dim3((unsigned)((cap > 0 && cap < n_items) ? cap : n_items));
 }
 
+// Occupancy clamp for the single-wave rho-shaped blocks.  The waves of a pass are few
+// per SIMD (about items / (4 x CUs)); if the previous kernel's tail frees some CUs
+// early, the dispatcher would pack those CUs up to their register-limited occupancy and
+// leave the rest short.  Reserving unused LDS per block caps the blocks per CU at
+// 4 x ceil(items / (4 x CUs)), so every CU gets its share wherever the waves land.
+size_t occupancy_clamp_lds(int32_t n_blocks) {
+  static int cus = 0, lds_per_cu = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        cus <= 0 || lds_per_cu <= 0) {
+      cus = -1;
+    }
+  }
+  if (cus <= 0) return 0;
+  const int64_t per_simd = (n_blocks + 4LL * cus - 1) / (4LL * cus);
+  const int64_t per_cu = 4 * std::max<int64_t>(per_simd, 1);
+  const size_t bytes = (size_t)(lds_per_cu / per_cu) / 256 * 256;
+  return std::min<size_t>(bytes, 64 * 1024);
+}
+
 template <int NPL, int KC, bool CACHE, bool VJP>
 void launch_rho_f32_t(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                       const double* z, const double* q, const int32_t* m, const float* gF,
                       hipStream_t st) {
-  hipLaunchKernelGGL((rho_f32_kernel<NPL, KC, CACHE, VJP>), grid_for(s.n_rho_items, s.rho_grid_cap), dim3(64),
-                     0, st, w, x, y, z, q, m, gF, s.n_total, s.n_rho_items);
+  const dim3 grid = grid_for(s.n_rho_items, s.rho_grid_cap);
+  const size_t lds = s.rho_clamp ? occupancy_clamp_lds((int32_t)grid.x) : 0;
+  hipLaunchKernelGGL((rho_f32_kernel<NPL, KC, CACHE, VJP>), grid, dim3(64), lds, st, w, x, y, z, q, m, gF, s.n_total,
+                     s.n_rho_items, s.rho_grid_cap > 0 ? 1 : 0);
 }
 
 template <int NPL, int KC, bool VJP>
 void launch_rho_f64_t(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                       const double* z, const double* q, const int32_t* m, const double* gF,
                       hipStream_t st) {
-  hipLaunchKernelGGL((rho_f64_kernel<NPL, KC, VJP>), grid_for(s.n_rho_items, s.rho_grid_cap), dim3(64), 0, st,
-                     w, x, y, z, q, m, gF, s.n_total, s.n_rho_items);
+  const dim3 grid = grid_for(s.n_rho_items, s.rho_grid_cap);
+  const size_t lds = s.rho_clamp ? occupancy_clamp_lds((int32_t)grid.x) : 0;
+  hipLaunchKernelGGL((rho_f64_kernel<NPL, KC, VJP>), grid, dim3(64), lds, st, w, x, y, z, q, m, gF, s.n_total,
+                     s.n_rho_items, s.rho_grid_cap > 0 ? 1 : 0);
 }
 
 // Particle-tile pass over every (tile, k-range) item; VJP selects adjoint pass B1.
@@ -912,9 +983,7 @@ void tile_pass_f32(const LaunchShape& s, const WsView& w, const double* x, const
     case 1608: launch_rho_f32_t<16, 8, CACHE, VJP>(s, w, x, y, z, q, m, g, st); break;
     case 808: launch_rho_f32_t<8, 8, CACHE, VJP>(s, w, x, y, z, q, m, g, st); break;
     case 1604: launch_rho_f32_t<16, 4, CACHE, VJP>(s, w, x, y, z, q, m, g, st); break;
-    case 3202: launch_rho_f32_t<32, 2, CACHE, VJP>(s, w, x, y, z, q, m, g, st); break;
-    case 1208: launch_rho_f32_t<12, 8, CACHE, VJP>(s, w, x, y, z, q, m, g, st); break;
-    case 2404: launch_rho_f32_t<24, 4, CACHE, VJP>(s, w, x, y, z, q, m, g, st); break;
+    case 804: launch_rho_f32_t<8, 4, CACHE, VJP>(s, w, x, y, z, q, m, g, st); break;
     default: break;
   }
 }

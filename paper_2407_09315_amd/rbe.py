@@ -148,6 +148,10 @@ class Plan:
             tiles = lookup(precision, phase_mode, batch.B, self.n_total, self.p_total)
         if tiles is not None:
             check(self.lib.rbe_plan_set_tiles(self.handle, int(tiles[0]), int(tiles[1])), "rbe_plan_set_tiles")
+            if len(tiles) > 2:
+                check(self.lib.rbe_plan_set_grid_caps(self.handle, int(tiles[2]), 0), "rbe_plan_set_grid_caps")
+            if len(tiles) > 3:
+                check(self.lib.rbe_plan_set_occupancy_clamp(self.handle, int(tiles[3])), "rbe_plan_set_occupancy_clamp")
         self._alloc()
 
     def _alloc(self):
@@ -170,18 +174,28 @@ class Plan:
         rho = torch.empty((self.p_total, 2), dtype=torch.float64, device=self.device)
         F = torch.empty((3, self.n_total), dtype=self.force_dtype, device=self.device)
         U = torch.empty(self.batch.B, dtype=torch.float64, device=self.device)
-        rv, fv = ctypes.c_int32(), ctypes.c_int32()
+        rv, fv, cap = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         rms, fms = ctypes.c_double(), ctypes.c_double()
         check(self.lib.rbe_plan_tune(self.handle, _ptr(x), _ptr(y), _ptr(z), _ptr(q), _ptr(m), _ptr(w),
                                      _ptr(rho), _ptr(F), _ptr(U), _ptr(self.ws), _stream(stream), reps,
-                                     ctypes.byref(rv), ctypes.byref(fv), ctypes.byref(rms), ctypes.byref(fms)),
+                                     ctypes.byref(rv), ctypes.byref(fv), ctypes.byref(cap), ctypes.byref(rms),
+                                     ctypes.byref(fms)),
               "rbe_plan_tune")
-        return {"rho_variant": rv.value, "force_variant": fv.value, "rho_ms": rms.value, "force_ms": fms.value}
+        return {"rho_variant": rv.value, "force_variant": fv.value, "rho_grid_cap": cap.value,
+                "occupancy_clamp": self.tiles()[3], "rho_ms": rms.value, "force_ms": fms.value}
 
     def tiles(self):
+        """(rho_variant, force_variant, rho_grid_cap, occupancy_clamp)."""
         a, b = ctypes.c_int32(), ctypes.c_int32()
         check(self.lib.rbe_plan_get_tiles(self.handle, ctypes.byref(a), ctypes.byref(b)), "rbe_plan_get_tiles")
-        return a.value, b.value
+        c, d = ctypes.c_int32(), ctypes.c_int32()
+        check(self.lib.rbe_plan_get_grid_caps(self.handle, ctypes.byref(c), ctypes.byref(d)), "rbe_plan_get_grid_caps")
+        e = ctypes.c_int32()
+        check(self.lib.rbe_plan_get_occupancy_clamp(self.handle, ctypes.byref(e)), "rbe_plan_get_occupancy_clamp")
+        return a.value, b.value, c.value, e.value
+
+    def set_occupancy_clamp(self, on: bool):
+        check(self.lib.rbe_plan_set_occupancy_clamp(self.handle, 1 if on else 0), "rbe_plan_set_occupancy_clamp")
 
     def num_variants(self):
         a, b = ctypes.c_int32(), ctypes.c_int32()

@@ -47,12 +47,12 @@ def save_cache(entries: dict, path: str | None = None) -> None:
 
 
 def lookup(precision: str, phase_mode: str, B: int, n_total: int, p_total: int, cache: dict | None = None):
-    """(rho_variant, force_variant) for this shape, or None for the built-in defaults."""
+    """(rho_variant, force_variant, rho_grid_cap, occupancy_clamp) for this shape, or None (defaults)."""
     cache = load_cache() if cache is None else cache
     key = shape_key(precision, phase_mode, B, n_total, p_total)
     if key in cache:
         e = cache[key]
-        return e["rho_variant"], e["force_variant"]
+        return e["rho_variant"], e["force_variant"], e.get("rho_grid_cap", 0), e.get("occupancy_clamp", 1)
     want_mode = key.split("|")[1]
     best, best_d = None, None
     for k, e in cache.items():
@@ -63,7 +63,8 @@ def lookup(precision: str, phase_mode: str, B: int, n_total: int, p_total: int, 
             continue
         d = abs(math.log(max(int(n[2:]), 1)) - math.log(max(n_total, 1)))
         if best_d is None or d < best_d:
-            best, best_d = (e["rho_variant"], e["force_variant"]), d
+            best, best_d = (e["rho_variant"], e["force_variant"], e.get("rho_grid_cap", 0),
+                            e.get("occupancy_clamp", 1)), d
     return best
 
 

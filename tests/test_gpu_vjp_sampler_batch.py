@@ -147,7 +147,8 @@ def test_batched_equals_single(precision):
     alphas = reps.alphas + [0.7, 0.2]
     ps = [100] * 10 + [5, 0]
     batch = Batch.from_sizes([s.n for s in systems], ps, [s.L for s in systems], alphas)
-    plan = Plan(batch, precision=precision, device=dev())
+    tiles = (0, 1)     # the same kernel variants for the batch and the single systems
+    plan = Plan(batch, precision=precision, device=dev(), tiles=tiles)
     m, w = plan.sample_k_device(6000, 0)
     cat = [to_dev(np.concatenate([getattr(s, a) for s in systems])) for a in ("x", "y", "z", "q")]
     F, U, rho = plan.forward(*cat, m, w)
@@ -157,7 +158,7 @@ def test_batched_equals_single(precision):
     no = ko = 0
     for b, s in enumerate(systems):
         P = ps[b]
-        sp = Plan(Batch.single(s.n, P, s.L, alphas[b]), precision=precision, device=dev())
+        sp = Plan(Batch.single(s.n, P, s.L, alphas[b]), precision=precision, device=dev(), tiles=tiles)
         Fs, Us, rs = sp.forward(*particles(s), to_dev(mh[ko:ko + P], torch.int32), to_dev(wh[ko:ko + P]))
         torch.cuda.synchronize()
         assert np.array_equal(Fs.cpu().numpy(), F[:, no:no + s.n]), b
