@@ -125,7 +125,13 @@ def main():
     log(f"fp32_mixed: {res['fp32']['wall_s'] * 1e3:.3f} ms/step")
     res["fp64"] = run_form(torch, Plan, Batch, X, s.L, alpha, P, "fp64", "recompute", args.steps, args.warmup)
     log(f"fp64: {res['fp64']['wall_s'] * 1e3:.3f} ms/step")
-    extra = {}
+    res["fp32_phase"] = run_form(torch, Plan, Batch, X, s.L, alpha, P, "fp32", "recompute", args.steps, args.warmup)
+    log(f"fp32 (FP32 phases): {res['fp32_phase']['wall_s'] * 1e3:.3f} ms/step")
+    r = res["fp32_phase"]
+    extra = {"fp32_phase_P100": {"ms_per_step": round(r["wall_s"] * 1e3, 4),
+                                 "G_terms_per_s": round(terms / r["wall_s"] / 1e9, 3),
+                                 "rho_kernel_ms": round(r["t_rho_s"] * 1e3, 4),
+                                 "force_kernel_ms": round(r["t_force_s"] * 1e3, 4), "tiles": r["tiles"]}}
     if not args.quick:
         r = run_form(torch, Plan, Batch, X, s.L, alpha, P, "fp32_mixed", "cached", max(5, args.steps // 5), 3)
         extra["fp32_mixed_cached_phase_P100"] = {"ms_per_step": r["wall_s"] * 1e3, "G_terms_per_s": terms / r["wall_s"] / 1e9,
@@ -235,7 +241,9 @@ def cpu_baseline(s, P, res):
             "kind": "oracle", "sample": f"full evaluation (rho + F + U) of the same 1M-atom system and P={P} "
                                         f"wave vectors, {reps} repetitions, {dt:.2f} s each"}
     errs = {}
-    for key, prec in (("fp32", "fp32_mixed"), ("fp64", "fp64")):
+    for key, prec in (("fp32", "fp32_mixed"), ("fp64", "fp64"), ("fp32_phase", "fp32")):
+        if key not in res:
+            continue
         r = res[key]
         if not np.array_equal(r["m"], m):
             F_ref2, U_ref2, rho_ref2 = oracle.force_energy(s.x, s.y, s.z, s.q, r["m"], r["w"], s.L)

@@ -38,7 +38,7 @@
  * periodic in each coordinate with period L.  Wave vectors m: int32, P_total
  * rows of (m_x, m_y, m_z).  rho: FP64 pairs (Re, Im), P_total rows.  Forces:
  * three planes of N_total values, F[d * N_total + i], in FP64 (RBE_FP64) or
- * FP32 (RBE_FP32_MIXED).  U: one FP64 value per system.
+ * FP32 (RBE_FP32_MIXED, RBE_FP32).  U: one FP64 value per system.
  *
  * Errors.  Every call returns an rbe_status.  Arguments are checked on the
  * host before anything is enqueued; on failure nothing is launched and
@@ -71,8 +71,16 @@ typedef enum {
 
 typedef enum {
     RBE_FP64 = 0,             /* FP64 phases, sin/cos and sums throughout */
-    RBE_FP32_MIXED = 1        /* exact fixed-point phases, FP32 sin/cos and per-wave sums,
+    RBE_FP32_MIXED = 1,       /* exact fixed-point phases, FP32 sin/cos and per-wave sums,
                                  FP64 cross-block sums and energy; FP32 forces */
+    RBE_FP32 = 2              /* as RBE_FP32_MIXED, but the phase m.r/L is formed in FP32
+                                 from fractional coordinates in [-1/2, 1/2]: fewer operations,
+                                 with a phase error that grows with |m| (about |m|_1 2^-25
+                                 turns).  Plans are refused (RBE_EUNSUPPORTED) for systems
+                                 with L sqrt(2 alpha) / (2 pi) > 16, the spread of sampled
+                                 m per component; caller-supplied m needs
+                                 |m_x| + |m_y| + |m_z| <= 510 (the hardware sine takes at
+                                 most 256 turns).  No phase cache */
 } rbe_precision;
 
 typedef enum {
@@ -138,12 +146,13 @@ rbe_status rbe_plan_num_variants(const rbe_plan *plan, int32_t *n_rho, int32_t *
 rbe_status rbe_plan_get_tiles(const rbe_plan *plan, int32_t *rho_variant, int32_t *force_variant);
 
 /*
- * Persistent grids.  rho_cap > 0 launches rho_cap single-wave blocks for the
- * rho-shaped passes, each pulling work items from an atomic counter in the
- * workspace until none are left (the last block resets the counter; calls that
- * overlap on one workspace race).  force_cap > 0 launches force_cap blocks for
- * the force-shaped passes, block b taking items b, b + force_cap, ...  0 (the
- * default) launches one block per work item.  Results do not depend on the caps.
+ * Persistent grids.  The rho-shaped passes run one wave per work item, four
+ * waves per block; rho_cap > 0 launches at most rho_cap waves (rounded up to
+ * whole blocks).  The force-shaped passes run one 256-thread block per work
+ * item; force_cap > 0 launches at most force_cap blocks.  Wave (block) j of a
+ * capped grid of G takes items j, j + G, j + 2G, ...  0 (the default) launches
+ * one wave (block) per item.  Results do not depend on the caps (each item
+ * writes its own partial-sum slots).
  */
 rbe_status rbe_plan_set_grid_caps(rbe_plan *plan, int32_t rho_cap, int32_t force_cap);
 rbe_status rbe_plan_get_grid_caps(const rbe_plan *plan, int32_t *rho_cap, int32_t *force_cap);
@@ -194,7 +203,7 @@ rbe_status rbe_structure_factor(const rbe_plan *plan, const double *x, const dou
  * Forces and energies from rho (Eq. frbe with per-k weights; Alg. 1 step 4).
  * w: (dev) P_total FP64 weights (S/P for RBE, exp(-k^2/4 alpha) for Ewald).
  * rho: (dev) the output of rbe_structure_factor for the same inputs.
- * F: (dev) 3*N_total values, FP64 for RBE_FP64 and FP32 for RBE_FP32_MIXED.
+ * F: (dev) 3*N_total values, FP64 for RBE_FP64, FP32 for RBE_FP32_MIXED and RBE_FP32.
  * U: (dev) B FP64 values.  In RBE_PHASE_CACHED mode the phase cache in ws
  * must come from rbe_structure_factor on the same positions.
  */

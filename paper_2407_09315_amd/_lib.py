@@ -15,7 +15,7 @@ import torch  # noqa: F401  (must be loaded before librbe.so, see module docstri
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librbe.so")
 
 RBE_OK, RBE_EINVAL, RBE_ENODEV, RBE_EHIP, RBE_EWORKSPACE, RBE_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-RBE_FP64, RBE_FP32_MIXED = 0, 1
+RBE_FP64, RBE_FP32_MIXED, RBE_FP32 = 0, 1, 2
 RBE_PHASE_AUTO, RBE_PHASE_RECOMPUTE, RBE_PHASE_CACHED = 0, 1, 2
 
 # name -> (restype, argtypes); every symbol that include/rbe.h declares

@@ -47,6 +47,11 @@ rbe_status device_ok() {
 }
 
 constexpr size_t kAlign = 256;
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+// Largest per-component spread of sampled |m| accepted for RBE_FP32 phases.  At 12 (a
+// 1M-atom box at alpha = 0.06) the measured force error is 5e-6 relative RMS; it grows
+// about linearly with the spread, so 16 keeps it below 1e-5.
+constexpr double kFp32PhaseMaxSigma = 16.0;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // ---------------------------------------------------------------- sampler tables
@@ -99,7 +104,7 @@ struct rbe_plan {
   bool cached = false;
   int rho_variant = 0;
   int force_variant = 1;
-  int32_t rho_grid_cap = 0;     // 0: one block per work item
+  int32_t rho_grid_cap = 0;     // waves; 0: one wave per work item
   int32_t rho_clamp = 1;        // occupancy clamp of the rho-shaped passes
   int32_t force_grid_cap = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // optional kernel timing events
@@ -113,7 +118,7 @@ struct rbe_plan {
   std::vector<double> cdf;
   // workspace layout (byte offsets)
   size_t off_sys = 0, off_rho = 0, off_force = 0, off_ksys = 0, off_cdf = 0, off_part = 0,
-         off_xy = 0, off_cache = 0, off_sched = 0, total = 0;
+         off_xy = 0, off_cache = 0, total = 0;
   size_t ws_bytes = 0;      // workspace size: the largest layout over all variants
   int64_t n_partials = 0;   // complex slots
   int64_t n_cache = 0;      // (cos, sin) pairs
@@ -121,7 +126,7 @@ struct rbe_plan {
   int64_t n_total() const { return sys_off[B]; }
   int64_t p_total() const { return k_off[B]; }
   RhoVariant rv() const {
-    return precision == RBE_FP32_MIXED ? kRhoVariantsF32[rho_variant] : kRhoVariantsF64[rho_variant];
+    return precision == RBE_FP64 ? kRhoVariantsF64[rho_variant] : kRhoVariantsF32[rho_variant];
   }
 };
 
@@ -155,19 +160,36 @@ void build_layout(rbe_plan* p) {
     s.cache_off = cache;
     if (p->cached) cache += (int64_t)s.n * s.p;
     for (int32_t l = 0; l < s.p; ++l) p->ksys[(size_t)(s.k_off + l)] = b;
-    if (s.p > 0 && s.ntiles > 0) {
-      const int nr = (s.p + rv.krange - 1) / rv.krange;
-      int chunk = (s.p + nr - 1) / nr;
-      chunk = (chunk + rv.kc - 1) / rv.kc * rv.kc;
-      for (int32_t t = 0; t < s.ntiles; ++t)
-        for (int32_t k0 = 0; k0 < s.p; k0 += chunk)
-          p->rho_items.push_back(RhoItem{b, t, k0, std::min(chunk, s.p - k0)});
-    }
     const int nf = std::max(1, (s.n + fchunk - 1) / fchunk);
     for (int f = 0; f < nf; ++f) {
       const int p0 = f * fchunk;
       p->force_items.push_back(ForceItem{b, p0, std::max(0, std::min(fchunk, s.n - p0)), f == 0 ? 1 : 0});
     }
+  }
+  // rho items.  A system's wave vectors are cut into ranges of whole KC-chunks whose chunk
+  // counts differ by at most one (at most krange vectors each).  Items are ordered
+  // range-major with the longer ranges first, so the hardware dispatcher starts the
+  // longest waves first and the short ones fill the tail.
+  {
+    struct Range { int32_t b, k0, nk, chunks; };
+    std::vector<Range> ranges;
+    for (int32_t b = 0; b < p->B; ++b) {
+      const SysDesc& s = p->sys[b];
+      if (s.p <= 0 || s.ntiles <= 0) continue;
+      const int nr = (s.p + rv.krange - 1) / rv.krange;
+      const int nch = (s.p + rv.kc - 1) / rv.kc;
+      int c0 = 0;
+      for (int r = 0; r < nr; ++r) {
+        const int cr = nch / nr + (r < nch % nr ? 1 : 0);
+        const int k0 = c0 * rv.kc;
+        ranges.push_back(Range{b, k0, std::min(cr * rv.kc, s.p - k0), cr});
+        c0 += cr;
+      }
+    }
+    std::stable_sort(ranges.begin(), ranges.end(),
+                     [](const Range& a, const Range& c) { return a.chunks > c.chunks; });
+    for (const Range& r : ranges)
+      for (int32_t t = 0; t < p->sys[r.b].ntiles; ++t) p->rho_items.push_back(RhoItem{r.b, t, r.k0, r.nk});
   }
   // sampler tables: [S][c_-M .. c_M] per system
   p->cdf.clear();
@@ -200,7 +222,6 @@ void build_layout(rbe_plan* p) {
   p->off_part = o;  o = align_up(o + 2 * sizeof(double) * (size_t)p->n_partials);
   p->off_xy = o;    o = align_up(o + 2 * sizeof(double) * (size_t)p->p_total());
   p->off_cache = o; o = align_up(o + 2 * sizeof(float) * (size_t)p->n_cache);
-  p->off_sched = o; o = align_up(o + 2 * sizeof(uint32_t));
   p->total = std::max<size_t>(o, kAlign);
 }
 
@@ -215,7 +236,6 @@ WsView view_of(const rbe_plan* p, void* ws) {
   w.partials = reinterpret_cast<double*>(b + p->off_part);
   w.xy = reinterpret_cast<double*>(b + p->off_xy);
   w.cache = reinterpret_cast<float*>(b + p->off_cache);
-  w.sched = reinterpret_cast<uint32_t*>(b + p->off_sched);
   return w;
 }
 
@@ -336,7 +356,8 @@ rbe_status rbe_plan_create(int32_t B, const int64_t* sys_off, const int64_t* k_o
   *out = nullptr;
   if (B <= 0) return fail(RBE_EINVAL, "B must be > 0 (got %d)", B);
   if (!sys_off || !k_off || !L || !alpha) return fail(RBE_EINVAL, "NULL batch array");
-  if (precision != RBE_FP64 && precision != RBE_FP32_MIXED) return fail(RBE_EINVAL, "unknown precision %d", precision);
+  if (precision != RBE_FP64 && precision != RBE_FP32_MIXED && precision != RBE_FP32)
+    return fail(RBE_EINVAL, "unknown precision %d", precision);
   if (phase_mode < RBE_PHASE_AUTO || phase_mode > RBE_PHASE_CACHED) return fail(RBE_EINVAL, "unknown phase mode %d", phase_mode);
   if (phase_mode == RBE_PHASE_CACHED && precision != RBE_FP32_MIXED)
     return fail(RBE_EUNSUPPORTED, "the phase cache exists for RBE_FP32_MIXED only");
@@ -348,6 +369,12 @@ rbe_status rbe_plan_create(int32_t B, const int64_t* sys_off, const int64_t* k_o
       return fail(RBE_EINVAL, "system %d too large", b);
     if (!finite_pos(L[b]) || !finite_pos(alpha[b]))
       return fail(RBE_EINVAL, "system %d: L and alpha must be finite and > 0", b);
+    // FP32 phases: the rounding error grows with |m|, whose spread under the sampling
+    // density is sigma_m = L sqrt(2 alpha) / (2 pi) per component.
+    if (precision == RBE_FP32 && L[b] * std::sqrt(2.0 * alpha[b]) / kTwoPi > kFp32PhaseMaxSigma)
+      return fail(RBE_EUNSUPPORTED,
+                  "system %d: RBE_FP32 phases need L sqrt(2 alpha) / (2 pi) <= %.0f (got %.1f); use RBE_FP32_MIXED",
+                  b, kFp32PhaseMaxSigma, L[b] * std::sqrt(2.0 * alpha[b]) / kTwoPi);
   }
   rbe_plan* p = new rbe_plan();
   p->B = B;
@@ -361,7 +388,7 @@ rbe_status rbe_plan_create(int32_t B, const int64_t* sys_off, const int64_t* k_o
   p->cached = phase_mode == RBE_PHASE_CACHED;
   // The workspace is sized for the largest layout over all variants, so the
   // autotuner can switch variants without reallocating.
-  const int nr = precision == RBE_FP32_MIXED ? kNumRhoVariantsF32 : kNumRhoVariantsF64;
+  const int nr = precision == RBE_FP64 ? kNumRhoVariantsF64 : kNumRhoVariantsF32;
   size_t most = 0;
   for (int r = 0; r < nr; ++r)
     for (int f = 0; f < kNumForceVariants; ++f) {
@@ -382,7 +409,7 @@ size_t rbe_plan_workspace_bytes(const rbe_plan* p) { return p ? p->ws_bytes : 0;
 
 rbe_status rbe_plan_num_variants(const rbe_plan* p, int32_t* n_rho, int32_t* n_force) {
   if (!p || !n_rho || !n_force) return fail(RBE_EINVAL, "NULL argument");
-  *n_rho = p->precision == RBE_FP32_MIXED ? kNumRhoVariantsF32 : kNumRhoVariantsF64;
+  *n_rho = p->precision == RBE_FP64 ? kNumRhoVariantsF64 : kNumRhoVariantsF32;
   *n_force = kNumForceVariants;
   return RBE_OK;
 }
@@ -415,7 +442,7 @@ rbe_status rbe_plan_get_grid_caps(const rbe_plan* p, int32_t* rho_cap, int32_t* 
 
 rbe_status rbe_plan_set_tiles(rbe_plan* p, int32_t rv, int32_t fv) {
   if (!p) return fail(RBE_EINVAL, "plan is NULL");
-  const int nr = p->precision == RBE_FP32_MIXED ? kNumRhoVariantsF32 : kNumRhoVariantsF64;
+  const int nr = p->precision == RBE_FP64 ? kNumRhoVariantsF64 : kNumRhoVariantsF32;
   if (rv < -1 || rv >= nr) return fail(RBE_EINVAL, "rho variant %d out of range [0, %d)", rv, nr);
   if (fv < -1 || fv >= kNumForceVariants) return fail(RBE_EINVAL, "force variant %d out of range", fv);
   if (rv >= 0) p->rho_variant = rv;
@@ -443,9 +470,6 @@ rbe_status rbe_plan_upload(const rbe_plan* p, void* ws, void* stream) {
     hipError_t e = hipMemcpyAsync(b + c.off, c.src, c.bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(plan upload)");
   }
-  // the dynamic-grid counters start at zero (each launch leaves them at zero)
-  hipError_t em = hipMemsetAsync(b + p->off_sched, 0, 2 * sizeof(uint32_t), s);
-  if (em != hipSuccess) return hip_fail(em, "hipMemsetAsync(plan upload)");
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(plan upload)");
   return RBE_OK;
@@ -530,7 +554,7 @@ rbe_status rbe_plan_tune(rbe_plan* p, const double* x, const double* y, const do
     *force_out = tf / (float)reps;
     return r;
   };
-  const int nr = p->precision == RBE_FP32_MIXED ? kNumRhoVariantsF32 : kNumRhoVariantsF64;
+  const int nr = p->precision == RBE_FP64 ? kNumRhoVariantsF64 : kNumRhoVariantsF32;
   int best_r = p->rho_variant, best_f = p->force_variant;
   float best_rms = 1e30f, best_fms = 1e30f;
   rbe_status r = RBE_OK;

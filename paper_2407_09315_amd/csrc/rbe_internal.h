@@ -41,11 +41,13 @@ struct ForceItem {
 };
 
 // Kernel variant tables (the autotuner picks one entry of each).
-struct RhoVariant { int npl; int kc; int krange; };   // particles per lane, k per chunk, k per item
+// rho: particles per lane, wave vectors per chunk, at most krange wave vectors per work item
+// (a system's wave vectors are cut into ranges of whole chunks whose counts differ by <= 1)
+struct RhoVariant { int npl; int kc; int krange; };
 struct ForceVariant { int nplf; };                       // particles per lane (256-thread blocks)
 
-constexpr int kNumRhoVariantsF32 = 6;
-constexpr int kNumRhoVariantsF64 = 5;
+constexpr int kNumRhoVariantsF32 = 7;
+constexpr int kNumRhoVariantsF64 = 7;
 constexpr int kNumForceVariants = 3;
 extern const RhoVariant kRhoVariantsF32[kNumRhoVariantsF32];
 extern const RhoVariant kRhoVariantsF64[kNumRhoVariantsF64];
@@ -65,7 +67,6 @@ struct WsView {
   double* partials;      // complex partial sums (rho pass, then VJP pass B1)
   double* xy;            // P_total complex values (VJP X + iY)
   float* cache;          // (cos, sin) phase cache, FP32_MIXED + CACHED only
-  uint32_t* sched;       // two work-pulling counters of the dynamic rho-pass grid (zero between launches)
 };
 
 struct LaunchShape {

@@ -33,9 +33,9 @@ namespace rbe {
 
 // {particles per lane, wave vectors per chunk, wave vectors per work item}
 const RhoVariant kRhoVariantsF32[kNumRhoVariantsF32] = {
-    {16, 8, 56}, {8, 8, 104}, {16, 4, 52}, {8, 8, 56}, {8, 8, 32}, {8, 4, 28}};
+    {8, 8, 56}, {8, 8, 40}, {8, 8, 32}, {8, 8, 104}, {16, 8, 56}, {8, 4, 28}, {8, 4, 12}};
 const RhoVariant kRhoVariantsF64[kNumRhoVariantsF64] = {
-    {8, 4, 52}, {4, 4, 100}, {8, 4, 100}, {4, 8, 104}, {8, 2, 50}};
+    {8, 2, 50}, {8, 2, 34}, {8, 4, 52}, {8, 4, 36}, {8, 4, 100}, {4, 4, 100}, {4, 8, 104}};
 const ForceVariant kForceVariants[kNumForceVariants] = {{1}, {2}, {4}};
 
 namespace {
@@ -64,6 +64,34 @@ __device__ inline float turns_arg(uint32_t t) {
 __device__ inline uint32_t phase_u32(int32_t mx, int32_t my, int32_t mz, uint32_t ux, uint32_t uy, uint32_t uz) {
   return (uint32_t)mx * ux + (uint32_t)my * uy + (uint32_t)mz * uz;
 }
+
+// Phase arithmetic of the FP32 passes.  Both give the argument of v_sin_f32 / v_cos_f32,
+// which take revolutions.
+//   Phase<false> (RBE_FP32_MIXED): 32-bit fixed-point fractions; m.s mod 1 is exact,
+//     then truncated to 23 bits (3 integer multiplies, add3, alignbit per term).
+//   Phase<true> (RBE_FP32): fractions centred in [-1/2, 1/2] held in FP32 and the phase
+//     m.s by an FMA chain (3 ops per term).  Its rounding error grows with |m.s|, and
+//     v_sin / v_cos accept |m.s| <= 256 turns.
+template <bool FPH> struct Phase;
+template <> struct Phase<false> {
+  using Coord = uint32_t;
+  __device__ static inline Coord coord(double x, double invL) { return fixed_fraction(x, invL); }
+  __device__ static inline float arg(int32_t mx, int32_t my, int32_t mz, float, float, float, Coord ux,
+                                     Coord uy, Coord uz) {
+    return turns_arg(phase_u32(mx, my, mz, ux, uy, uz));
+  }
+};
+template <> struct Phase<true> {
+  using Coord = float;
+  __device__ static inline Coord coord(double x, double invL) {
+    const double v = x * invL;
+    return (float)(v - rint(v));
+  }
+  __device__ static inline float arg(int32_t, int32_t, int32_t, float fx, float fy, float fz, Coord ux,
+                                     Coord uy, Coord uz) {
+    return fmaf(fx, ux, fmaf(fy, uy, fz * uz));
+  }
+};
 
 // sin and cos of 2 pi r for |r| <= 1/2 (turns), FP64.  With q = rint(4 r) in {-2..2}
 // and f = r - q/4 (exact, |f| <= 1/8): exp(2 pi i r) = i^q exp(2 pi i f), and
@@ -173,31 +201,21 @@ __device__ inline void wave_reduce_scatter(T (&v)[V], int lane) {
   ReduceScatter<0, V / 2, T, V>::run(v, lane);
 }
 
-// Work-item scheduling of the rho-shaped passes.  Static: block b takes items b, b + grid,
-// ...  Dynamic (persistent grids): each single-wave block pulls the next item from an
-// atomic counter in the workspace, so waves on faster or less crowded SIMDs take more
-// items; the last block to finish resets the counters for the next launch.  The
-// partial-sum slot of an item is fixed by the item, so results do not depend on which
-// block ran it.
-__device__ inline int32_t pull_item(uint32_t* sched) {
-  int32_t v = 0;
-  if (threadIdx.x == 0) v = (int32_t)atomicAdd(&sched[0], 1u);
-  // lane 0's value, marked wave-uniform so everything derived from it stays scalar
-  return __builtin_amdgcn_readfirstlane(v);
-}
-__device__ inline int32_t first_item(uint32_t* sched, int dyn) {
-  return dyn ? pull_item(sched) : (int32_t)blockIdx.x;
-}
-__device__ inline int32_t next_item(uint32_t* sched, int dyn, int32_t item) {
-  return dyn ? pull_item(sched) : item + (int32_t)gridDim.x;
-}
-__device__ inline void finish_items(uint32_t* sched, int dyn) {
-  if (dyn && threadIdx.x == 0) {
-    const uint32_t done = atomicAdd(&sched[1], 1u);
-    if (done == gridDim.x - 1) {
-      atomicExch(&sched[0], 0u);
-      atomicExch(&sched[1], 0u);
-    }
+// Rho-shaped passes run four independent waves per 256-thread block (one per SIMD) so
+// that every SIMD of a CU gets the same number of waves.  The waves sharing a SIMD come
+// from different blocks and would otherwise be served oldest first: the oldest finish
+// early and the last ones run alone, too few to hide latency (one wave keeps a SIMD
+// about half busy, four nearly fully).  Each wave therefore raises its issue priority
+// with the work it has left (most remaining chunks first, exact over the last three),
+// so the waves on a SIMD finish within about one chunk of each other.
+constexpr int kRhoWaves = 4;
+
+__device__ inline void remaining_priority(int chunks_left) {
+  switch (chunks_left) {
+    case 1: __builtin_amdgcn_s_setprio(0); break;
+    case 2: __builtin_amdgcn_s_setprio(1); break;
+    case 3: __builtin_amdgcn_s_setprio(2); break;
+    default: __builtin_amdgcn_s_setprio(3); break;
   }
 }
 
@@ -205,6 +223,17 @@ __device__ inline void finish_items(uint32_t* sched, int dyn) {
 template <int KC>
 __device__ inline void load_chunk(const int32_t* mk, int kc, int nk, int32_t (&mx)[KC], int32_t (&my)[KC],
                                   int32_t (&mz)[KC]) {
+  if (kc + KC <= nk) {
+    // whole chunk: 3 KC contiguous words (wide scalar loads)
+    const int32_t* r = mk + 3 * kc;
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      mx[c] = r[3 * c];
+      my[c] = r[3 * c + 1];
+      mz[c] = r[3 * c + 2];
+    }
+    return;
+  }
 #pragma unroll
   for (int c = 0; c < KC; ++c) {
     const int kk = min(kc + c, nk - 1);
@@ -220,32 +249,35 @@ __device__ inline void load_chunk(const int32_t* mk, int kc, int nk, int32_t (&m
 
 // With VJP, the same pass forms X_l + i Y_l = sum_i q_i (gF_i . m_l) exp(i theta_il)
 // (adjoint pass B1; the 2 pi / L of k_l is applied when the adjoint table is built).
-template <int NPL, int KC, bool CACHE, bool VJP>
-__global__ __launch_bounds__(64) void rho_f32_kernel(WsView w, const double* __restrict__ x,
+template <int NPL, int KC, bool CACHE, bool VJP, bool FPH>
+__global__ __launch_bounds__(256) void rho_f32_kernel(WsView w, const double* __restrict__ x,
                                                      const double* __restrict__ y,
                                                      const double* __restrict__ z,
                                                      const double* __restrict__ q,
                                                      const int32_t* __restrict__ m,
                                                      const float* __restrict__ gF, int64_t n_total,
-                                                     int32_t n_items, int dyn) {
-for (int32_t item = first_item(w.sched, dyn); item < n_items; item = next_item(w.sched, dyn, item)) {
+                                                     int32_t n_items) {
+// persistent grids (fewer waves than items) stride over the items in a fixed order
+const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+for (int32_t item = blockIdx.x * kRhoWaves + wave; item < n_items; item += gridDim.x * kRhoWaves) {
   const RhoItem it = w.rho_items[item];
   const SysDesc sd = w.sys[it.sys];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int first = it.tile * (64 * NPL);
   const int cnt = min(64 * NPL, sd.n - first);
   const double invL = 1.0 / sd.L;
 
-  uint32_t ux[NPL], uy[NPL], uz[NPL];
+  using Ph = Phase<FPH>;
+  typename Ph::Coord ux[NPL], uy[NPL], uz[NPL];
   float qv[NPL], qgx[VJP ? NPL : 1], qgy[VJP ? NPL : 1], qgz[VJP ? NPL : 1];
 #pragma unroll
   for (int j = 0; j < NPL; ++j) {
     const int li = j * 64 + lane;
     if (li < cnt) {
       const int64_t gi = sd.n_off + first + li;
-      ux[j] = fixed_fraction(x[gi], invL);
-      uy[j] = fixed_fraction(y[gi], invL);
-      uz[j] = fixed_fraction(z[gi], invL);
+      ux[j] = Ph::coord(x[gi], invL);
+      uy[j] = Ph::coord(y[gi], invL);
+      uz[j] = Ph::coord(z[gi], invL);
       qv[j] = (float)q[gi];
       if (VJP) {
         qgx[j] = qv[j] * gF[gi];
@@ -253,7 +285,7 @@ for (int32_t item = first_item(w.sched, dyn); item < n_items; item = next_item(w
         qgz[j] = qv[j] * gF[2 * n_total + gi];
       }
     } else {
-      ux[j] = uy[j] = uz[j] = 0u;
+      ux[j] = uy[j] = uz[j] = 0;
       qv[j] = 0.0f;
       if (VJP) qgx[j] = qgy[j] = qgz[j] = 0.0f;
     }
@@ -264,13 +296,19 @@ for (int32_t item = first_item(w.sched, dyn); item < n_items; item = next_item(w
   // wave vectors of the next chunk are loaded (scalar loads) one chunk ahead
   int32_t nmx[KC], nmy[KC], nmz[KC];
   load_chunk<KC>(mk, 0, it.nk, nmx, nmy, nmz);
+  const bool more_items = item + (int32_t)gridDim.x * kRhoWaves < n_items;
   for (int kc = 0; kc < it.nk; kc += KC) {
+    remaining_priority(more_items ? 4 : (it.nk - kc + KC - 1) / KC);
     int32_t mx[KC], my[KC], mz[KC];
+    float fmx[KC], fmy[KC], fmz[KC];   // used by the FP32 phase only
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
       mx[c] = nmx[c];
       my[c] = nmy[c];
       mz[c] = nmz[c];
+      fmx[c] = (float)mx[c];
+      fmy[c] = (float)my[c];
+      fmz[c] = (float)mz[c];
     }
     if (kc + KC < it.nk) load_chunk<KC>(mk, kc + KC, it.nk, nmx, nmy, nmz);
     float acc[2 * KC];
@@ -285,7 +323,7 @@ for (int32_t item = first_item(w.sched, dyn); item < n_items; item = next_item(w
       for (int jj = 0; jj < kPairs; ++jj)
 #pragma unroll
         for (int c = 0; c < KC; ++c)
-          a[jj][c] = turns_arg(phase_u32(mx[c], my[c], mz[c], ux[j0 + jj], uy[j0 + jj], uz[j0 + jj]));
+          a[jj][c] = Ph::arg(mx[c], my[c], mz[c], fmx[c], fmy[c], fmz[c], ux[j0 + jj], uy[j0 + jj], uz[j0 + jj]);
 #pragma unroll
       for (int jj = 0; jj < kPairs; ++jj)
 #pragma unroll
@@ -300,7 +338,7 @@ for (int32_t item = first_item(w.sched, dyn); item < n_items; item = next_item(w
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
           float wt = qv[j];
-          if (VJP) wt = fmaf(qgx[j], (float)mx[c], fmaf(qgy[j], (float)my[c], qgz[j] * (float)mz[c]));
+          if (VJP) wt = fmaf(qgx[j], fmx[c], fmaf(qgy[j], fmy[c], qgz[j] * fmz[c]));
           acc[c] = fmaf(wt, cs[jj][c], acc[c]);
           acc[KC + c] = fmaf(wt, sn[jj][c], acc[KC + c]);
           if (CACHE) {
@@ -326,23 +364,24 @@ for (int32_t item = first_item(w.sched, dyn); item < n_items; item = next_item(w
     }
   }
   }
-  finish_items(w.sched, dyn);
 }
 
 // ------------------------------------------------------------------ rho pass, FP64
 
 template <int NPL, int KC, bool VJP>
-__global__ __launch_bounds__(64) void rho_f64_kernel(WsView w, const double* __restrict__ x,
+__global__ __launch_bounds__(256) void rho_f64_kernel(WsView w, const double* __restrict__ x,
                                                      const double* __restrict__ y,
                                                      const double* __restrict__ z,
                                                      const double* __restrict__ q,
                                                      const int32_t* __restrict__ m,
                                                      const double* __restrict__ gF, int64_t n_total,
-                                                     int32_t n_items, int dyn) {
-for (int32_t item = first_item(w.sched, dyn); item < n_items; item = next_item(w.sched, dyn, item)) {
+                                                     int32_t n_items) {
+// persistent grids (fewer waves than items) stride over the items in a fixed order
+const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+for (int32_t item = blockIdx.x * kRhoWaves + wave; item < n_items; item += gridDim.x * kRhoWaves) {
   const RhoItem it = w.rho_items[item];
   const SysDesc sd = w.sys[it.sys];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int first = it.tile * (64 * NPL);
   const int cnt = min(64 * NPL, sd.n - first);
   const double invL = 1.0 / sd.L;
@@ -373,7 +412,9 @@ for (int32_t item = first_item(w.sched, dyn); item < n_items; item = next_item(w
   double* part = w.partials + 2 * sd.part_off;
   const int32_t* mk = m + 3 * (sd.k_off + it.k0);
 
+  const bool more_items = item + (int32_t)gridDim.x * kRhoWaves < n_items;
   for (int kc = 0; kc < it.nk; kc += KC) {
+    remaining_priority(more_items ? 4 : (it.nk - kc + KC - 1) / KC);
     double mx[KC], my[KC], mz[KC];
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
@@ -411,7 +452,6 @@ for (int32_t item = first_item(w.sched, dyn); item < n_items; item = next_item(w
     }
   }
   }
-  finish_items(w.sched, dyn);
 }
 
 // ------------------------------------------------------------------ cross-tile reduction
@@ -472,7 +512,7 @@ struct TabF32 {
   float b;              // c_l * C'_l
 };
 
-template <int NPLF, bool CACHED>
+template <int NPLF, bool CACHED, bool FPH>
 __global__ __launch_bounds__(kForceBlock) void force_f32_kernel(
     WsView w, int64_t n_total, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const double* __restrict__ q, const int32_t* __restrict__ m,
@@ -488,7 +528,8 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
   const double kscale = kTwoPi * invL;
   const double vol = sd.L * sd.L * sd.L;
 
-  uint32_t ux[NPLF], uy[NPLF], uz[NPLF];
+  using Ph = Phase<FPH>;
+  typename Ph::Coord ux[NPLF], uy[NPLF], uz[NPLF];
   float fx[NPLF], fy[NPLF], fz[NPLF];
   int li[NPLF];
 #pragma unroll
@@ -497,11 +538,11 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
     const bool ok = j * kForceBlock + tid < it.np;
     if (ok && !CACHED) {
       const int64_t gi = sd.n_off + li[j];
-      ux[j] = fixed_fraction(x[gi], invL);
-      uy[j] = fixed_fraction(y[gi], invL);
-      uz[j] = fixed_fraction(z[gi], invL);
+      ux[j] = Ph::coord(x[gi], invL);
+      uy[j] = Ph::coord(y[gi], invL);
+      uz[j] = Ph::coord(z[gi], invL);
     } else {
-      ux[j] = uy[j] = uz[j] = 0u;
+      ux[j] = uy[j] = uz[j] = 0;
     }
     fx[j] = fy[j] = fz[j] = 0.0f;
   }
@@ -550,7 +591,8 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         } else {
           float a[kUnroll];
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) a[u] = turns_arg(phase_u32(tb[u].mx, tb[u].my, tb[u].mz, ux[j], uy[j], uz[j]));
+          for (int u = 0; u < kUnroll; ++u)
+            a[u] = Ph::arg(tb[u].mx, tb[u].my, tb[u].mz, tb[u].fx, tb[u].fy, tb[u].fz, ux[j], uy[j], uz[j]);
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) sn[u] = __builtin_amdgcn_sinf(a[u]);
 #pragma unroll
@@ -713,7 +755,7 @@ struct TabAdjF32 {
   float z1r, z1i, z2r, z2i;
 };
 
-template <int NPLF>
+template <int NPLF, bool FPH>
 __global__ __launch_bounds__(kForceBlock) void vjp_b2_f32_kernel(
     WsView w, int64_t n_total, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const double* __restrict__ q, const int32_t* __restrict__ m,
@@ -730,21 +772,22 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
   const double vol = sd.L * sd.L * sd.L;
   const double gu = gU[it.sys];
 
-  uint32_t ux[NPLF], uy[NPLF], uz[NPLF];
+  using Ph = Phase<FPH>;
+  typename Ph::Coord ux[NPLF], uy[NPLF], uz[NPLF];
   float gx[NPLF], gy[NPLF], gz[NPLF], rx[NPLF], ry[NPLF], rz[NPLF], rq[NPLF];
 #pragma unroll
   for (int j = 0; j < NPLF; ++j) {
     const bool ok = j * kForceBlock + tid < it.np;
     if (ok) {
       const int64_t gi = sd.n_off + it.p0 + j * kForceBlock + tid;
-      ux[j] = fixed_fraction(x[gi], invL);
-      uy[j] = fixed_fraction(y[gi], invL);
-      uz[j] = fixed_fraction(z[gi], invL);
+      ux[j] = Ph::coord(x[gi], invL);
+      uy[j] = Ph::coord(y[gi], invL);
+      uz[j] = Ph::coord(z[gi], invL);
       gx[j] = gF[gi];
       gy[j] = gF[n_total + gi];
       gz[j] = gF[2 * n_total + gi];
     } else {
-      ux[j] = uy[j] = uz[j] = 0u;
+      ux[j] = uy[j] = uz[j] = 0;
       gx[j] = gy[j] = gz[j] = 0.0f;
     }
     rx[j] = ry[j] = rz[j] = rq[j] = 0.0f;
@@ -770,7 +813,7 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
       const TabAdjF32 tb = tab[e];
 #pragma unroll
       for (int j = 0; j < NPLF; ++j) {
-        const float a = turns_arg(phase_u32(tb.mx, tb.my, tb.mz, ux[j], uy[j], uz[j]));
+        const float a = Ph::arg(tb.mx, tb.my, tb.mz, tb.fx, tb.fy, tb.fz, ux[j], uy[j], uz[j]);
         const float sn = __builtin_amdgcn_sinf(a);
         const float cs = __builtin_amdgcn_cosf(a);
         const float gm = fmaf(gx[j], tb.fx, fmaf(gy[j], tb.fy, gz[j] * tb.fz));
@@ -932,12 +975,12 @@ dim3 grid_for(int32_t n_items, int32_t cap) {
   return dim3((unsigned)((cap > 0 && cap < n_items) ? cap : n_items));
 }
 
-// Occupancy clamp for the single-wave rho-shaped blocks.  The waves of a pass are few
-// per SIMD (about items / (4 x CUs)); if the previous kernel's tail frees some CUs
-// early, the dispatcher would pack those CUs up to their register-limited occupancy and
-// leave the rest short.  Reserving unused LDS per block caps the blocks per CU at
-// 4 x ceil(items / (4 x CUs)), so every CU gets its share wherever the waves land.
-size_t occupancy_clamp_lds(int32_t n_blocks) {
+// Occupancy clamp of the rho-shaped passes.  Their waves are few per SIMD (about
+// items / (4 x CUs)); if the previous kernel's tail frees some CUs early, the dispatcher
+// would pack those CUs up to their register-limited occupancy and leave the rest short.
+// Reserving unused LDS per block caps the 4-wave blocks per CU at
+// ceil(items / (4 x CUs)), so every CU gets its share wherever the blocks land.
+size_t occupancy_clamp_lds(int32_t n_waves) {
   static int cus = 0, lds_per_cu = 0;
   if (cus == 0) {
     int dev = 0;
@@ -949,41 +992,46 @@ size_t occupancy_clamp_lds(int32_t n_blocks) {
     }
   }
   if (cus <= 0) return 0;
-  const int64_t per_simd = (n_blocks + 4LL * cus - 1) / (4LL * cus);
-  const int64_t per_cu = 4 * std::max<int64_t>(per_simd, 1);
-  const size_t bytes = (size_t)(lds_per_cu / per_cu) / 256 * 256;
+  const int64_t per_simd = std::max<int64_t>((n_waves + 4LL * cus - 1) / (4LL * cus), 1);
+  const size_t bytes = (size_t)(lds_per_cu / per_simd) / 256 * 256;
   return std::min<size_t>(bytes, 64 * 1024);
 }
 
-template <int NPL, int KC, bool CACHE, bool VJP>
+// Blocks of the rho-shaped passes: one wave per item (at most cap waves when cap > 0),
+// kRhoWaves waves per block.
+dim3 rho_grid(int32_t n_items, int32_t cap) {
+  const int32_t waves = (cap > 0 && cap < n_items) ? cap : n_items;
+  return dim3((unsigned)((waves + kRhoWaves - 1) / kRhoWaves));
+}
+
+template <int NPL, int KC, bool CACHE, bool VJP, bool FPH>
 void launch_rho_f32_t(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                       const double* z, const double* q, const int32_t* m, const float* gF,
                       hipStream_t st) {
-  const dim3 grid = grid_for(s.n_rho_items, s.rho_grid_cap);
-  const size_t lds = s.rho_clamp ? occupancy_clamp_lds((int32_t)grid.x) : 0;
-  hipLaunchKernelGGL((rho_f32_kernel<NPL, KC, CACHE, VJP>), grid, dim3(64), lds, st, w, x, y, z, q, m, gF, s.n_total,
-                     s.n_rho_items, s.rho_grid_cap > 0 ? 1 : 0);
+  const dim3 grid = rho_grid(s.n_rho_items, s.rho_grid_cap);
+  const size_t lds = s.rho_clamp ? occupancy_clamp_lds((int32_t)grid.x * kRhoWaves) : 0;
+  hipLaunchKernelGGL((rho_f32_kernel<NPL, KC, CACHE, VJP, FPH>), grid, dim3(64 * kRhoWaves), lds, st, w, x, y, z,
+                     q, m, gF, s.n_total, s.n_rho_items);
 }
 
 template <int NPL, int KC, bool VJP>
 void launch_rho_f64_t(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                       const double* z, const double* q, const int32_t* m, const double* gF,
                       hipStream_t st) {
-  const dim3 grid = grid_for(s.n_rho_items, s.rho_grid_cap);
-  const size_t lds = s.rho_clamp ? occupancy_clamp_lds((int32_t)grid.x) : 0;
-  hipLaunchKernelGGL((rho_f64_kernel<NPL, KC, VJP>), grid, dim3(64), lds, st, w, x, y, z, q, m, gF, s.n_total,
-                     s.n_rho_items, s.rho_grid_cap > 0 ? 1 : 0);
+  const dim3 grid = rho_grid(s.n_rho_items, s.rho_grid_cap);
+  const size_t lds = s.rho_clamp ? occupancy_clamp_lds((int32_t)grid.x * kRhoWaves) : 0;
+  hipLaunchKernelGGL((rho_f64_kernel<NPL, KC, VJP>), grid, dim3(64 * kRhoWaves), lds, st, w, x, y, z, q, m, gF,
+                     s.n_total, s.n_rho_items);
 }
 
 // Particle-tile pass over every (tile, k-range) item; VJP selects adjoint pass B1.
-template <bool CACHE, bool VJP>
+template <bool CACHE, bool VJP, bool FPH>
 void tile_pass_f32(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                    const double* z, const double* q, const int32_t* m, const float* g, hipStream_t st) {
   switch (s.rv.npl * 100 + s.rv.kc) {
-    case 1608: launch_rho_f32_t<16, 8, CACHE, VJP>(s, w, x, y, z, q, m, g, st); break;
-    case 808: launch_rho_f32_t<8, 8, CACHE, VJP>(s, w, x, y, z, q, m, g, st); break;
-    case 1604: launch_rho_f32_t<16, 4, CACHE, VJP>(s, w, x, y, z, q, m, g, st); break;
-    case 804: launch_rho_f32_t<8, 4, CACHE, VJP>(s, w, x, y, z, q, m, g, st); break;
+    case 1608: launch_rho_f32_t<16, 8, CACHE, VJP, FPH>(s, w, x, y, z, q, m, g, st); break;
+    case 808: launch_rho_f32_t<8, 8, CACHE, VJP, FPH>(s, w, x, y, z, q, m, g, st); break;
+    case 804: launch_rho_f32_t<8, 4, CACHE, VJP, FPH>(s, w, x, y, z, q, m, g, st); break;
     default: break;
   }
 }
@@ -996,11 +1044,13 @@ void launch_tile_pass(const LaunchShape& s, const WsView& w, const double* x, co
     const float* g = static_cast<const float*>(gF);
     if constexpr (!VJP) {
       if (s.cached != 0) {
-        tile_pass_f32<true, false>(s, w, x, y, z, q, m, g, st);
+        tile_pass_f32<true, false, false>(s, w, x, y, z, q, m, g, st);
         return;
       }
     }
-    tile_pass_f32<false, VJP>(s, w, x, y, z, q, m, g, st);
+    tile_pass_f32<false, VJP, false>(s, w, x, y, z, q, m, g, st);
+  } else if (s.precision == RBE_FP32) {   // the plan rejects the phase cache here
+    tile_pass_f32<false, VJP, true>(s, w, x, y, z, q, m, static_cast<const float*>(gF), st);
   } else {
     const double* g = static_cast<const double*>(gF);
     switch (s.rv.npl * 100 + s.rv.kc) {
@@ -1025,11 +1075,11 @@ void truncation_rotation(int precision, double* c, double* s) {
   }
 }
 
-template <int NPLF, bool CACHED>
+template <int NPLF, bool CACHED, bool FPH>
 void force_f32_t(const LaunchShape& s, const WsView& w, const double* x, const double* y, const double* z,
                  const double* q, const int32_t* m, const double* wk, const double* rho, float* F, double* U,
                  double rc, double rs, uint64_t* counter, hipStream_t st) {
-  hipLaunchKernelGGL((force_f32_kernel<NPLF, CACHED>), grid_for(s.n_force_items, s.force_grid_cap),
+  hipLaunchKernelGGL((force_f32_kernel<NPLF, CACHED, FPH>), grid_for(s.n_force_items, s.force_grid_cap),
                      dim3(kForceBlock), 0, st, w, s.n_total, x, y, z, q, m, wk, rho, F, U, rc, rs,
                      s.n_force_items, counter);
 }
@@ -1074,16 +1124,23 @@ hipError_t launch_force(const LaunchShape& s, const WsView& w, const double* x, 
     float* Ff = static_cast<float*>(F);
     if (s.cached) {
       switch (s.fv.nplf) {
-        case 1: force_f32_t<1, true>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
-        case 2: force_f32_t<2, true>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
-        default: force_f32_t<4, true>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
+        case 1: force_f32_t<1, true, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
+        case 2: force_f32_t<2, true, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
+        default: force_f32_t<4, true, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
       }
     } else {
       switch (s.fv.nplf) {
-        case 1: force_f32_t<1, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
-        case 2: force_f32_t<2, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
-        default: force_f32_t<4, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
+        case 1: force_f32_t<1, false, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
+        case 2: force_f32_t<2, false, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
+        default: force_f32_t<4, false, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
       }
+    }
+  } else if (s.precision == RBE_FP32) {
+    float* Ff = static_cast<float*>(F);
+    switch (s.fv.nplf) {
+      case 1: force_f32_t<1, false, true>(s, w, x, y, z, q, m, wk, rho, Ff, U, 1.0, 0.0, counter, st); break;
+      case 2: force_f32_t<2, false, true>(s, w, x, y, z, q, m, wk, rho, Ff, U, 1.0, 0.0, counter, st); break;
+      default: force_f32_t<4, false, true>(s, w, x, y, z, q, m, wk, rho, Ff, U, 1.0, 0.0, counter, st); break;
     }
   } else {
     double* Fd = static_cast<double*>(F);
@@ -1117,14 +1174,18 @@ hipError_t launch_vjp(const LaunchShape& s, const WsView& w, const double* x, co
   if (s.n_force_items == 0) return hipSuccess;
   const dim3 grid = grid_for(s.n_force_items, s.force_grid_cap), block(kForceBlock);
   const int32_t ni = s.n_force_items;
-  if (s.precision == RBE_FP32_MIXED) {
+  if (s.precision == RBE_FP32_MIXED || s.precision == RBE_FP32) {
     const float* g = static_cast<const float*>(gF);
     float* r = static_cast<float*>(gr);
     float* qq = static_cast<float*>(gq);
-    switch (s.fv.nplf) {
-      case 1: hipLaunchKernelGGL((vjp_b2_f32_kernel<1>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, rc, rs, ni); break;
-      case 2: hipLaunchKernelGGL((vjp_b2_f32_kernel<2>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, rc, rs, ni); break;
-      default: hipLaunchKernelGGL((vjp_b2_f32_kernel<4>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, rc, rs, ni); break;
+    const bool fph = s.precision == RBE_FP32;
+    switch (s.fv.nplf * 2 + (fph ? 1 : 0)) {
+      case 2: hipLaunchKernelGGL((vjp_b2_f32_kernel<1, false>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, rc, rs, ni); break;
+      case 3: hipLaunchKernelGGL((vjp_b2_f32_kernel<1, true>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, rc, rs, ni); break;
+      case 4: hipLaunchKernelGGL((vjp_b2_f32_kernel<2, false>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, rc, rs, ni); break;
+      case 5: hipLaunchKernelGGL((vjp_b2_f32_kernel<2, true>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, rc, rs, ni); break;
+      case 9: hipLaunchKernelGGL((vjp_b2_f32_kernel<4, true>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, rc, rs, ni); break;
+      default: hipLaunchKernelGGL((vjp_b2_f32_kernel<4, false>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, rc, rs, ni); break;
     }
   } else {
     const double* g = static_cast<const double*>(gF);

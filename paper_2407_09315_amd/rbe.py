@@ -13,10 +13,10 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (RBE_FP32_MIXED, RBE_FP64, RBE_PHASE_AUTO, RBE_PHASE_CACHED,  # noqa: F401
+from ._lib import (RBE_FP32, RBE_FP32_MIXED, RBE_FP64, RBE_PHASE_AUTO, RBE_PHASE_CACHED,  # noqa: F401
                    RBE_PHASE_RECOMPUTE, RBEError, check, load)
 
-PRECISIONS = {"fp64": RBE_FP64, "fp32_mixed": RBE_FP32_MIXED}
+PRECISIONS = {"fp64": RBE_FP64, "fp32_mixed": RBE_FP32_MIXED, "fp32": RBE_FP32}
 PHASE_MODES = {"auto": RBE_PHASE_AUTO, "recompute": RBE_PHASE_RECOMPUTE, "cached": RBE_PHASE_CACHED}
 
 
@@ -129,8 +129,10 @@ class Plan:
 
     def __init__(self, batch: Batch, precision: str = "fp32_mixed", phase_mode: str = "auto",
                  device=None, tiles="auto"):
-        """tiles: (rho_variant, force_variant), "auto" (the tuning cache, else the
-        library defaults) or None (library defaults)."""
+        """precision: "fp64", "fp32_mixed" (exact fixed-point phases, FP32 sin/cos) or
+        "fp32" (FP32 phases, fewer operations, phase error growing with |m|).
+        tiles: (rho_variant, force_variant[, rho_grid_cap[, occupancy_clamp]]), "auto"
+        (the tuning cache, else the library defaults) or None (library defaults)."""
         self.lib = load()
         self.batch = batch
         self.precision = precision
@@ -204,7 +206,7 @@ class Plan:
 
     @property
     def force_dtype(self):
-        return torch.float32 if self.precision == "fp32_mixed" else torch.float64
+        return torch.float64 if self.precision == "fp64" else torch.float32
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -91,6 +91,31 @@ def test_plan_validation():
     assert st == _lib.RBE_EINVAL
     st, _ = _create(1, [0, 10], [0, 5], [3.0], [1.0], prec=0, mode=2)
     assert st == _lib.RBE_EUNSUPPORTED
+    # the phase cache exists for the fixed-point FP32 phases only
+    st, _ = _create(1, [0, 10], [0, 5], [3.0], [1.0], prec=_lib.RBE_FP32, mode=2)
+    assert st == _lib.RBE_EUNSUPPORTED
+    for prec in (_lib.RBE_FP64, _lib.RBE_FP32_MIXED, _lib.RBE_FP32):
+        st, h = _create(1, [0, 10], [0, 5], [3.0], [1.0], prec=prec)
+        assert st == 0
+        lib.rbe_plan_destroy(h)
+
+
+def test_fp32_phase_box_guard():
+    """RBE_FP32 phases are refused once the spread of sampled m, L sqrt(2 alpha) / (2 pi), exceeds 16."""
+    lib = _lib.load()
+    ok = [(217.0534689782871, 0.06), (144.1289350602584, 0.08)]     # 1M electrolyte, 300k water
+    bad = [(467.627523158581, 0.06), (2 * np.pi * 16.01 / np.sqrt(0.2), 0.1)]
+    for L, a in ok:
+        st, h = _create(1, [0, 10], [0, 5], [L], [a], prec=_lib.RBE_FP32)
+        assert st == 0, (L, a)
+        lib.rbe_plan_destroy(h)
+    for L, a in bad:
+        st, _ = _create(1, [0, 10], [0, 5], [L], [a], prec=_lib.RBE_FP32)
+        assert st == _lib.RBE_EUNSUPPORTED, (L, a)
+        assert b"RBE_FP32_MIXED" in lib.rbe_last_error()
+        st, h = _create(1, [0, 10], [0, 5], [L], [a], prec=_lib.RBE_FP32_MIXED)
+        assert st == 0
+        lib.rbe_plan_destroy(h)
     assert lib.rbe_sample_k(1, 0, -1.0, 0.1, 4, None, None, None) == _lib.RBE_EINVAL
     assert b"L and alpha" in lib.rbe_last_error()
 

@@ -16,7 +16,7 @@ from parity_util import note, particles, to_dev
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
 def test_graph_replays_match_eager(precision):
     reps = ri.c5_replicas(B=4)
     systems = reps.systems
@@ -42,7 +42,7 @@ def test_graph_replays_match_eager(precision):
             assert int(counter.item()) == r + 1
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
 def test_persistent_grid_caps_bitwise(precision):
     s, alpha, P = ri.c4_differentiable()
     m, w, _ = rbe_sample_k(5, 0, s.L, alpha, P)

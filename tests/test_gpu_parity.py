@@ -1,6 +1,7 @@
 """GPU parity of the forward path (rho, F, U) against the FP64 oracle.
 
-FP64 form: every measure <= 1e-12.  FP32-mixed form: every measure <= 1e-5.
+FP64 form: every measure <= 1e-12.  FP32 forms (fixed-point phases "fp32_mixed" and
+FP32 phases "fp32"): every measure <= 1e-5.
 Cases: the 3,000-charge box, the paper's electrolyte and water shapes, the
 300k water box, the 200k differentiable box and the 1M electrolyte at P = 100
 and 200 in full; the 10M electrolyte on all of rho and on sampled forces;
@@ -19,7 +20,7 @@ from parity_util import (FP32_TOL, FP64_TOL, dev, force_err, note, particles, re
                          to_dev)
 
 pytestmark = pytest.mark.gpu
-TOL = {"fp64": FP64_TOL, "fp32_mixed": FP32_TOL}
+TOL = {"fp64": FP64_TOL, "fp32_mixed": FP32_TOL, "fp32": FP32_TOL}
 
 
 def _run(s, alpha, m, w, precision, phase_mode="auto", tiles=None):
@@ -50,14 +51,14 @@ SMALL = {
 }
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
 @pytest.mark.parametrize("case", sorted(SMALL))
 def test_small_parity(case, precision):
     s, alpha, P = SMALL[case]()
     _check(case, s, alpha, P, 2001, precision)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 1023, 1025, 5000])
 def test_ragged_sizes(n, precision):
     s = ri.random_charges(n, 9.0, 40 + n)
@@ -76,7 +77,7 @@ def test_ragged_sizes(n, precision):
         _check(f"ragged n={n}", s, 0.3, P, 17 + P, precision)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
 def test_all_variants(precision):
     s, alpha, P = ri.c1_small()
     plan = Plan(Batch.single(s.n, P, s.L, alpha), precision=precision, device=dev())
@@ -86,7 +87,7 @@ def test_all_variants(precision):
             _check("c1 variants", s, alpha, P, 2001, precision, tiles=(rv, fv))
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
 def test_degenerate(precision):
     # P = 0: zero force, zero energy; n = 0: empty force, zero energy
     s = ri.random_charges(100, 5.0, 1)
@@ -100,7 +101,7 @@ def test_degenerate(precision):
     assert F.numel() == 0 and float(U[0]) == 0.0 and np.all(rho.cpu().numpy() == 0)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
 def test_two_charge_closed_form(precision):
     L, d = 7.0, 1.3
     s = ri.System(np.array([0.0, d]), np.zeros(2), np.zeros(2), np.array([1.0, -1.0]), L)
@@ -113,7 +114,7 @@ def test_two_charge_closed_form(precision):
     assert rel(F[0, 0], c * k * np.sin(k * d)) < tol and rel(F[0, 1], -c * k * np.sin(k * d)) < tol
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
 def test_full_ewald_kspace(precision):
     """Deterministic Ewald k-space sum over |m_d| <= 10 (Eq. long) through the same kernels."""
     s, alpha, _ = ri.c1_small()
@@ -143,7 +144,7 @@ LARGE = {
 }
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
 @pytest.mark.parametrize("case", sorted(LARGE))
 def test_large_parity(case, precision):
     s, alpha, P = LARGE[case]()
@@ -155,7 +156,7 @@ def c3a():
     return ri.c3a_electrolyte()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
 @pytest.mark.parametrize("P", [100, 200])
 def test_c3a_1M_parity(c3a, P, precision):
     s, alpha, _ = c3a
@@ -167,6 +168,7 @@ def test_c3a_1M_cached_phase(c3a):
     _check("c3a_1M cached", s, alpha, 100, 2003, "fp32_mixed", phase_mode="cached")
 
 
+# RBE_FP32 phases are refused for this box (sampled |m| spread 25.8 > 16)
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
 def test_c3b_10M_sampled(precision):
     s, alpha, P = ri.c3b_electrolyte()
@@ -200,7 +202,7 @@ def test_fp32_truncation_rotation_is_removed(c3a):
     assert abs(mean) < 0.25 * np.pi * 2 ** -23
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
 def test_bitwise_deterministic(c3a, precision):
     s, alpha, _ = c3a
     m, w, _ = rbe_sample_k(2003, 0, s.L, alpha, 100)

@@ -42,7 +42,7 @@ def _grad_err(g, g_ref):
     return float(np.sqrt(np.sum((g - g_ref) ** 2) / np.sum(g_ref ** 2)))
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
 def test_vjp_vs_oracle_small(precision):
     s, alpha, P = ri.c1_small()
     note(f"case vjp c1 {precision}")
@@ -54,7 +54,7 @@ def test_vjp_vs_oracle_small(precision):
     assert er < tol and eq < tol
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
 def test_vjp_vs_oracle_c4(precision):
     s, alpha, P = ri.c4_differentiable()
     note(f"case vjp c4 {precision}")
@@ -100,7 +100,7 @@ def test_vjp_finite_differences_c4():
     assert err.max() < 1e-6
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
 def test_autograd_function(precision):
     s, alpha, P = ri.e3_electrolyte()
     m, w, _ = rbe_sample_k(9, 0, s.L, alpha, P)
@@ -140,7 +140,7 @@ def test_device_sampler_bit_exact():
         off += P
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
 def test_batched_equals_single(precision):
     reps = ri.c5_replicas(B=10)
     systems = reps.systems + [ri.random_charges(3, 4.0, 1), ri.uniform_pm1(2000, 20.0, 2)]
