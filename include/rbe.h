@@ -251,6 +251,19 @@ rbe_status rbe_plan_tune(rbe_plan *plan, const double *x, const double *y, const
                          double *force_ms);
 
 /*
+ * One whole evaluation of every system of the plan (Alg. 1 steps 2-4), enqueued
+ * on `stream` without host synchronisation: device sampling
+ * (rbe_sample_k_device), rbe_structure_factor and rbe_kspace_force.  Arguments
+ * and step_counter as for rbe_graph_create below; m and w are outputs (the drawn
+ * wave vectors and weights).  Back-to-back calls keep the device busy without
+ * the per-launch cost of a graph replay.
+ */
+rbe_status rbe_evaluate(const rbe_plan *plan, uint64_t seed, uint64_t stream_base,
+                        uint64_t *step_counter, const double *x, const double *y, const double *z,
+                        const double *q, int32_t *m, double *w, double *rho, void *F, double *U,
+                        void *ws, void *stream);
+
+/*
  * Capture one whole evaluation of every system of the plan -- device sampling
  * (rbe_sample_k_device), rbe_structure_factor and rbe_kspace_force -- into a
  * HIP graph, for replay with rbe_graph_launch at the cost of one launch.

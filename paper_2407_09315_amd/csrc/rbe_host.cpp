@@ -166,11 +166,19 @@ void build_layout(rbe_plan* p) {
       p->force_items.push_back(ForceItem{b, p0, std::max(0, std::min(fchunk, s.n - p0)), f == 0 ? 1 : 0});
     }
   }
-  // rho items.  A system's wave vectors are cut into ranges of whole KC-chunks whose chunk
-  // counts differ by at most one (at most krange vectors each).  Items are ordered
+  // rho items.  Cooperative variants (one block per CU sharing work through LDS): one item
+  // per (tile, KC-chunk), tile-major, so a wave's consecutive claims reuse its tile.
+  // Otherwise a system's wave vectors are cut into ranges of whole KC-chunks whose chunk
+  // counts differ by at most one (at most krange vectors each), and items are ordered
   // range-major with the longer ranges first, so the hardware dispatcher starts the
   // longest waves first and the short ones fill the tail.
-  {
+  if (rv.wpb == 16) {
+    for (int32_t b = 0; b < p->B; ++b) {
+      const SysDesc& s = p->sys[b];
+      for (int32_t t = 0; t < s.ntiles; ++t)
+        for (int32_t k0 = 0; k0 < s.p; k0 += rv.kc) p->rho_items.push_back(RhoItem{b, t, k0, std::min(rv.kc, s.p - k0)});
+    }
+  } else {
     struct Range { int32_t b, k0, nk, chunks; };
     std::vector<Range> ranges;
     for (int32_t b = 0; b < p->B; ++b) {
@@ -614,11 +622,12 @@ rbe_status rbe_plan_set_timing_events(rbe_plan* p, void* rho_begin, void* rho_en
   return RBE_OK;
 }
 
-rbe_status rbe_graph_create(const rbe_plan* p, uint64_t seed, uint64_t stream_base, uint64_t* step_counter,
-                            const double* x, const double* y, const double* z, const double* q, int32_t* m,
-                            double* w, double* rho, void* F, double* U, void* ws, rbe_graph** out) {
-  if (out == nullptr) return fail(RBE_EINVAL, "out is NULL");
-  *out = nullptr;
+namespace {
+
+// Arguments of one whole evaluation (device sampling, rho pass, reduction, force pass).
+rbe_status check_evaluation(const rbe_plan* p, const double* x, const double* y, const double* z, const double* q,
+                            const int32_t* m, const double* w, const double* rho, const void* F, const double* U,
+                            void* ws) {
   rbe_status st = check_common(p, ws);
   if (st != RBE_OK) return st;
   if (!p->sampler_ok) return fail(RBE_EINVAL, "a system's zero-vector probability exceeds 1/2 (box too small for alpha)");
@@ -626,17 +635,47 @@ rbe_status rbe_graph_create(const rbe_plan* p, uint64_t seed, uint64_t stream_ba
   if (!need(x, n) || !need(y, n) || !need(z, n) || !need(q, n) || !need(F, n))
     return fail(RBE_EINVAL, "NULL position/charge/force array");
   if (!need(m, P) || !need(w, P) || !need(rho, P) || U == nullptr) return fail(RBE_EINVAL, "NULL m, w, rho or U");
+  return RBE_OK;
+}
+
+hipError_t enqueue_evaluation(const rbe_plan* p, uint64_t seed, uint64_t stream_base, uint64_t* step_counter,
+                              const double* x, const double* y, const double* z, const double* q, int32_t* m,
+                              double* w, double* rho, void* F, double* U, void* ws, hipStream_t st) {
+  const LaunchShape shape = shape_of(p);
+  const WsView view = view_of(p, ws);
+  hipError_t e = launch_sample(shape, view, seed, stream_base, step_counter, m, w, st);
+  if (e == hipSuccess) e = launch_rho(shape, view, x, y, z, q, m, rho, st);
+  if (e == hipSuccess) e = launch_force(shape, view, x, y, z, q, m, w, rho, F, U, step_counter, st);
+  return e;
+}
+
+}  // namespace
+
+rbe_status rbe_evaluate(const rbe_plan* p, uint64_t seed, uint64_t stream_base, uint64_t* step_counter,
+                        const double* x, const double* y, const double* z, const double* q, int32_t* m, double* w,
+                        double* rho, void* F, double* U, void* ws, void* stream) {
+  rbe_status st = check_evaluation(p, x, y, z, q, m, w, rho, F, U, ws);
+  if (st != RBE_OK) return st;
+  hipError_t e = enqueue_evaluation(p, seed, stream_base, step_counter, x, y, z, q, m, w, rho, F, U, ws,
+                                    static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "rbe_evaluate launch");
+  return RBE_OK;
+}
+
+rbe_status rbe_graph_create(const rbe_plan* p, uint64_t seed, uint64_t stream_base, uint64_t* step_counter,
+                            const double* x, const double* y, const double* z, const double* q, int32_t* m,
+                            double* w, double* rho, void* F, double* U, void* ws, rbe_graph** out) {
+  if (out == nullptr) return fail(RBE_EINVAL, "out is NULL");
+  *out = nullptr;
+  rbe_status st = check_evaluation(p, x, y, z, q, m, w, rho, F, U, ws);
+  if (st != RBE_OK) return st;
   hipStream_t cs;
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
-  const LaunchShape shape = shape_of(p);
-  const WsView view = view_of(p, ws);
   hipGraph_t graph = nullptr;
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
   if (e == hipSuccess) {
-    hipError_t le = launch_sample(shape, view, seed, stream_base, step_counter, m, w, cs);
-    if (le == hipSuccess) le = launch_rho(shape, view, x, y, z, q, m, rho, cs);
-    if (le == hipSuccess) le = launch_force(shape, view, x, y, z, q, m, w, rho, F, U, step_counter, cs);
+    hipError_t le = enqueue_evaluation(p, seed, stream_base, step_counter, x, y, z, q, m, w, rho, F, U, ws, cs);
     e = hipStreamEndCapture(cs, &graph);
     if (le != hipSuccess) e = le;
   }

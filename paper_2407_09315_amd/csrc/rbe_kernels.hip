@@ -33,9 +33,11 @@ namespace rbe {
 
 // {particles per lane, wave vectors per chunk, wave vectors per work item}
 const RhoVariant kRhoVariantsF32[kNumRhoVariantsF32] = {
-    {8, 8, 56}, {8, 8, 40}, {8, 8, 32}, {8, 8, 104}, {16, 8, 56}, {8, 4, 28}, {8, 4, 12}};
+    {8, 8, 56, 4}, {8, 8, 40, 4}, {8, 8, 32, 4}, {8, 8, 104, 4}, {16, 8, 56, 4},
+    {8, 4, 28, 4}, {8, 4, 12, 4}, {8, 8, 8, 16}, {8, 4, 4, 16}};
 const RhoVariant kRhoVariantsF64[kNumRhoVariantsF64] = {
-    {8, 2, 50}, {8, 2, 34}, {8, 4, 52}, {8, 4, 36}, {8, 4, 100}, {4, 4, 100}, {4, 8, 104}};
+    {8, 4, 52, 4}, {8, 2, 50, 4}, {8, 2, 34, 4}, {8, 4, 36, 4}, {8, 4, 100, 4},
+    {4, 4, 100, 4}, {4, 8, 104, 4}, {4, 4, 4, 16}};
 const ForceVariant kForceVariants[kNumForceVariants] = {{1}, {2}, {4}};
 
 namespace {
@@ -201,14 +203,24 @@ __device__ inline void wave_reduce_scatter(T (&v)[V], int lane) {
   ReduceScatter<0, V / 2, T, V>::run(v, lane);
 }
 
-// Rho-shaped passes run four independent waves per 256-thread block (one per SIMD) so
-// that every SIMD of a CU gets the same number of waves.  The waves sharing a SIMD come
-// from different blocks and would otherwise be served oldest first: the oldest finish
-// early and the last ones run alone, too few to hide latency (one wave keeps a SIMD
-// about half busy, four nearly fully).  Each wave therefore raises its issue priority
-// with the work it has left (most remaining chunks first, exact over the last three),
-// so the waves on a SIMD finish within about one chunk of each other.
-constexpr int kRhoWaves = 4;
+// Work schedules of the rho-shaped passes (template parameter WPB, waves per block).
+//
+// WPB = 4: four independent waves per 256-thread block, one per SIMD, each taking one
+// (tile, k-range) item (capped grids stride over the items).  The waves sharing a SIMD
+// come from different blocks and the hardware serves them oldest first, so the oldest
+// finish early and the last ones run alone, too few to hide latency (one resident wave
+// keeps a SIMD about half busy, four nearly fully).  Each wave therefore raises its issue
+// priority with the chunks it has left (most remaining first, exact over the last three).
+//
+// WPB = 16: one 1024-thread block per CU (four waves per SIMD) over single-chunk items in
+// tile-major order.  Each block owns an equal contiguous range of items, split into 16
+// home ranges, one per wave.  A wave claims items from its home range through an LDS
+// counter and, once that is used up, claims from the other waves' ranges in turn, so all
+// sixteen waves stay busy until the CU's share is done.  Particles are reloaded only when
+// the claimed item's tile differs from the one in registers.  Every claim is an atomic
+// increment of a finite range and a wave stops after one fruitless pass over all ranges,
+// so every wave exits.  Results do not depend on which wave runs an item.
+constexpr int kCoopWaves = 16;
 
 __device__ inline void remaining_priority(int chunks_left) {
   switch (chunks_left) {
@@ -218,6 +230,54 @@ __device__ inline void remaining_priority(int chunks_left) {
     default: __builtin_amdgcn_s_setprio(3); break;
   }
 }
+
+template <int WPB> struct RhoSchedule;
+
+template <> struct RhoSchedule<4> {
+  int32_t item, n_items, stride;
+  __device__ RhoSchedule(int32_t n, int32_t wave, int32_t*) : item(-1), n_items(n), stride(0) {
+    item = (int32_t)blockIdx.x * 4 + wave;
+    stride = (int32_t)gridDim.x * 4;
+  }
+  __device__ int32_t first() { return item < n_items ? item : -1; }
+  __device__ int32_t next() {
+    item += stride;
+    return item < n_items ? item : -1;
+  }
+  // issue priority for a wave with chunks_left chunks of its current item to go
+  __device__ void priority(int chunks_left) const {
+    remaining_priority(item + stride < n_items ? 4 : chunks_left);
+  }
+};
+
+template <> struct RhoSchedule<kCoopWaves> {
+  int32_t* next_;   // LDS: next item of each home range, then the range ends
+  int32_t wave, victim;
+  __device__ RhoSchedule(int32_t n, int32_t wv, int32_t* lds) : next_(lds), wave(wv), victim(wv) {
+    if (threadIdx.x < kCoopWaves) {
+      const int64_t b0 = (int64_t)n * blockIdx.x / gridDim.x;
+      const int64_t len = (int64_t)n * (blockIdx.x + 1) / gridDim.x - b0;
+      const int t = threadIdx.x;
+      lds[t] = (int32_t)(b0 + len * t / kCoopWaves);
+      lds[kCoopWaves + t] = (int32_t)(b0 + len * (t + 1) / kCoopWaves);
+    }
+    __syncthreads();
+  }
+  __device__ int32_t claim() {
+    for (;;) {
+      int32_t idx = 0;
+      if ((threadIdx.x & 63) == 0) idx = atomicAdd(&next_[victim], 1);
+      idx = __builtin_amdgcn_readfirstlane(idx);
+      const int32_t end = __builtin_amdgcn_readfirstlane(next_[kCoopWaves + victim]);
+      if (idx < end) return idx;
+      victim = (victim + 1) & (kCoopWaves - 1);
+      if (victim == wave) return -1;
+    }
+  }
+  __device__ int32_t first() { return claim(); }
+  __device__ int32_t next() { return claim(); }
+  __device__ void priority(int) const {}
+};
 
 // Wave vectors kc .. kc+KC-1 of an item (zero past its end); uniform, so scalar loads.
 template <int KC>
@@ -249,208 +309,228 @@ __device__ inline void load_chunk(const int32_t* mk, int kc, int nk, int32_t (&m
 
 // With VJP, the same pass forms X_l + i Y_l = sum_i q_i (gF_i . m_l) exp(i theta_il)
 // (adjoint pass B1; the 2 pi / L of k_l is applied when the adjoint table is built).
-template <int NPL, int KC, bool CACHE, bool VJP, bool FPH>
-__global__ __launch_bounds__(256) void rho_f32_kernel(WsView w, const double* __restrict__ x,
-                                                     const double* __restrict__ y,
-                                                     const double* __restrict__ z,
-                                                     const double* __restrict__ q,
-                                                     const int32_t* __restrict__ m,
-                                                     const float* __restrict__ gF, int64_t n_total,
-                                                     int32_t n_items) {
-// persistent grids (fewer waves than items) stride over the items in a fixed order
-const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
-for (int32_t item = blockIdx.x * kRhoWaves + wave; item < n_items; item += gridDim.x * kRhoWaves) {
-  const RhoItem it = w.rho_items[item];
-  const SysDesc sd = w.sys[it.sys];
+template <int NPL, int KC, bool CACHE, bool VJP, bool FPH, int WPB>
+__global__ __launch_bounds__(64 * WPB) void rho_f32_kernel(WsView w, const double* __restrict__ x,
+                                                          const double* __restrict__ y,
+                                                          const double* __restrict__ z,
+                                                          const double* __restrict__ q,
+                                                          const int32_t* __restrict__ m,
+                                                          const float* __restrict__ gF, int64_t n_total,
+                                                          int32_t n_items) {
+  __shared__ int32_t sched_lds[WPB == kCoopWaves ? 2 * kCoopWaves : 1];
   const int lane = threadIdx.x & 63;
-  const int first = it.tile * (64 * NPL);
-  const int cnt = min(64 * NPL, sd.n - first);
-  const double invL = 1.0 / sd.L;
+  const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+  RhoSchedule<WPB> sched(n_items, wave, sched_lds);
 
+  // particles per step: the cooperative blocks are limited to 128 VGPRs per wave
+  constexpr int PAIRS = kPairs;
   using Ph = Phase<FPH>;
   typename Ph::Coord ux[NPL], uy[NPL], uz[NPL];
   float qv[NPL], qgx[VJP ? NPL : 1], qgy[VJP ? NPL : 1], qgz[VJP ? NPL : 1];
-#pragma unroll
-  for (int j = 0; j < NPL; ++j) {
-    const int li = j * 64 + lane;
-    if (li < cnt) {
-      const int64_t gi = sd.n_off + first + li;
-      ux[j] = Ph::coord(x[gi], invL);
-      uy[j] = Ph::coord(y[gi], invL);
-      uz[j] = Ph::coord(z[gi], invL);
-      qv[j] = (float)q[gi];
-      if (VJP) {
-        qgx[j] = qv[j] * gF[gi];
-        qgy[j] = qv[j] * gF[n_total + gi];
-        qgz[j] = qv[j] * gF[2 * n_total + gi];
-      }
-    } else {
-      ux[j] = uy[j] = uz[j] = 0;
-      qv[j] = 0.0f;
-      if (VJP) qgx[j] = qgy[j] = qgz[j] = 0.0f;
-    }
-  }
-  double* part = w.partials + 2 * sd.part_off;
-  const int32_t* mk = m + 3 * (sd.k_off + it.k0);
+  int32_t cur_sys = -1, cur_tile = -1;   // tile held in registers
 
-  // wave vectors of the next chunk are loaded (scalar loads) one chunk ahead
-  int32_t nmx[KC], nmy[KC], nmz[KC];
-  load_chunk<KC>(mk, 0, it.nk, nmx, nmy, nmz);
-  const bool more_items = item + (int32_t)gridDim.x * kRhoWaves < n_items;
-  for (int kc = 0; kc < it.nk; kc += KC) {
-    remaining_priority(more_items ? 4 : (it.nk - kc + KC - 1) / KC);
-    int32_t mx[KC], my[KC], mz[KC];
-    float fmx[KC], fmy[KC], fmz[KC];   // used by the FP32 phase only
+  for (int32_t item = sched.first(); item >= 0; item = sched.next()) {
+    // the item index is wave-uniform; saying so keeps the item and its wave vectors in
+    // scalar registers and scalar loads
+    const RhoItem it = w.rho_items[__builtin_amdgcn_readfirstlane(item)];
+    const SysDesc sd = w.sys[it.sys];
+    const int first = it.tile * (64 * NPL);
+    const int cnt = min(64 * NPL, sd.n - first);
+    if (it.sys != cur_sys || it.tile != cur_tile) {
+      cur_sys = it.sys;
+      cur_tile = it.tile;
+      const double invL = 1.0 / sd.L;
 #pragma unroll
-    for (int c = 0; c < KC; ++c) {
-      mx[c] = nmx[c];
-      my[c] = nmy[c];
-      mz[c] = nmz[c];
-      fmx[c] = (float)mx[c];
-      fmy[c] = (float)my[c];
-      fmz[c] = (float)mz[c];
+      for (int j = 0; j < NPL; ++j) {
+        const int li = j * 64 + lane;
+        if (li < cnt) {
+          const int64_t gi = sd.n_off + first + li;
+          ux[j] = Ph::coord(x[gi], invL);
+          uy[j] = Ph::coord(y[gi], invL);
+          uz[j] = Ph::coord(z[gi], invL);
+          qv[j] = (float)q[gi];
+          if (VJP) {
+            qgx[j] = qv[j] * gF[gi];
+            qgy[j] = qv[j] * gF[n_total + gi];
+            qgz[j] = qv[j] * gF[2 * n_total + gi];
+          }
+        } else {
+          ux[j] = uy[j] = uz[j] = 0;
+          qv[j] = 0.0f;
+          if (VJP) qgx[j] = qgy[j] = qgz[j] = 0.0f;
+        }
+        // reload in groups of four particles: bounds the FP64 loads in flight (registers)
+        if (WPB == kCoopWaves && (j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
     }
-    if (kc + KC < it.nk) load_chunk<KC>(mk, kc + KC, it.nk, nmx, nmy, nmz);
-    float acc[2 * KC];
+    double* part = w.partials + 2 * sd.part_off;
+    const int32_t* mk = m + 3 * (sd.k_off + it.k0);
+
+    // wave vectors of the next chunk are loaded (scalar loads) one chunk ahead
+    int32_t nmx[KC], nmy[KC], nmz[KC];
+    load_chunk<KC>(mk, 0, it.nk, nmx, nmy, nmz);
+    for (int kc = 0; kc < it.nk; kc += KC) {
+      sched.priority((it.nk - kc + KC - 1) / KC);
+      int32_t mx[KC], my[KC], mz[KC];
+      float fmx[KC], fmy[KC], fmz[KC];   // used by the FP32 phase only
 #pragma unroll
-    for (int c = 0; c < 2 * KC; ++c) acc[c] = 0.0f;
+      for (int c = 0; c < KC; ++c) {
+        mx[c] = nmx[c];
+        my[c] = nmy[c];
+        mz[c] = nmz[c];
+        fmx[c] = (float)mx[c];
+        fmy[c] = (float)my[c];
+        fmz[c] = (float)mz[c];
+      }
+      if (kc + KC < it.nk) load_chunk<KC>(mk, kc + KC, it.nk, nmx, nmy, nmz);
+      float acc[2 * KC];
 #pragma unroll
-    for (int j0 = 0; j0 < NPL; j0 += kPairs) {
-      // kPairs particles against the KC wave vectors, stage by stage for instruction-level
-      // parallelism (kPairs * KC independent phase -> sin/cos -> FMA chains)
-      float a[kPairs][KC], sn[kPairs][KC], cs[kPairs][KC];
+      for (int c = 0; c < 2 * KC; ++c) acc[c] = 0.0f;
 #pragma unroll
-      for (int jj = 0; jj < kPairs; ++jj)
+      for (int j0 = 0; j0 < NPL; j0 += PAIRS) {
+        // PAIRS particles against the KC wave vectors, stage by stage for instruction-level
+        // parallelism (PAIRS * KC independent phase -> sin/cos -> FMA chains)
+        float a[PAIRS][KC], sn[PAIRS][KC], cs[PAIRS][KC];
 #pragma unroll
-        for (int c = 0; c < KC; ++c)
-          a[jj][c] = Ph::arg(mx[c], my[c], mz[c], fmx[c], fmy[c], fmz[c], ux[j0 + jj], uy[j0 + jj], uz[j0 + jj]);
+        for (int jj = 0; jj < PAIRS; ++jj)
 #pragma unroll
-      for (int jj = 0; jj < kPairs; ++jj)
+          for (int c = 0; c < KC; ++c)
+            a[jj][c] = Ph::arg(mx[c], my[c], mz[c], fmx[c], fmy[c], fmz[c], ux[j0 + jj], uy[j0 + jj], uz[j0 + jj]);
 #pragma unroll
-        for (int c = 0; c < KC; ++c) sn[jj][c] = __builtin_amdgcn_sinf(a[jj][c]);
+        for (int jj = 0; jj < PAIRS; ++jj)
 #pragma unroll
-      for (int jj = 0; jj < kPairs; ++jj)
+          for (int c = 0; c < KC; ++c) sn[jj][c] = __builtin_amdgcn_sinf(a[jj][c]);
 #pragma unroll
-        for (int c = 0; c < KC; ++c) cs[jj][c] = __builtin_amdgcn_cosf(a[jj][c]);
+        for (int jj = 0; jj < PAIRS; ++jj)
 #pragma unroll
-      for (int jj = 0; jj < kPairs; ++jj) {
-        const int j = j0 + jj;
+          for (int c = 0; c < KC; ++c) cs[jj][c] = __builtin_amdgcn_cosf(a[jj][c]);
 #pragma unroll
-        for (int c = 0; c < KC; ++c) {
-          float wt = qv[j];
-          if (VJP) wt = fmaf(qgx[j], fmx[c], fmaf(qgy[j], fmy[c], qgz[j] * fmz[c]));
-          acc[c] = fmaf(wt, cs[jj][c], acc[c]);
-          acc[KC + c] = fmaf(wt, sn[jj][c], acc[KC + c]);
-          if (CACHE) {
-            const int li = j * 64 + lane;
-            if (li < cnt && kc + c < it.nk) {
-              float2* cp = reinterpret_cast<float2*>(w.cache) + sd.cache_off +
-                           (int64_t)(it.k0 + kc + c) * sd.n + first + li;
-              *cp = make_float2(cs[jj][c], sn[jj][c]);
+        for (int jj = 0; jj < PAIRS; ++jj) {
+          const int j = j0 + jj;
+#pragma unroll
+          for (int c = 0; c < KC; ++c) {
+            float wt = qv[j];
+            if (VJP) wt = fmaf(qgx[j], fmx[c], fmaf(qgy[j], fmy[c], qgz[j] * fmz[c]));
+            acc[c] = fmaf(wt, cs[jj][c], acc[c]);
+            acc[KC + c] = fmaf(wt, sn[jj][c], acc[KC + c]);
+            if (CACHE) {
+              const int li = j * 64 + lane;
+              if (li < cnt && kc + c < it.nk) {
+                float2* cp = reinterpret_cast<float2*>(w.cache) + sd.cache_off +
+                             (int64_t)(it.k0 + kc + c) * sd.n + first + li;
+                *cp = make_float2(cs[jj][c], sn[jj][c]);
+              }
             }
           }
         }
       }
-    }
-    wave_reduce_scatter<2 * KC>(acc, lane);
-    if (lane < 2 * KC) {
-      const int vi = scatter_index(lane, Log2<2 * KC>::value);
-      const int c = vi % KC;
-      const int comp = vi / KC;
-      if (kc + c < it.nk) {
-        const int64_t kl = it.k0 + kc + c;
-        part[2 * (kl * sd.ntiles + it.tile) + comp] = (double)acc[0];
+      wave_reduce_scatter<2 * KC>(acc, lane);
+      if (lane < 2 * KC) {
+        const int vi = scatter_index(lane, Log2<2 * KC>::value);
+        const int c = vi % KC;
+        const int comp = vi / KC;
+        if (kc + c < it.nk) {
+          const int64_t kl = it.k0 + kc + c;
+          part[2 * (kl * sd.ntiles + it.tile) + comp] = (double)acc[0];
+        }
       }
     }
-  }
   }
 }
 
 // ------------------------------------------------------------------ rho pass, FP64
 
-template <int NPL, int KC, bool VJP>
-__global__ __launch_bounds__(256) void rho_f64_kernel(WsView w, const double* __restrict__ x,
-                                                     const double* __restrict__ y,
-                                                     const double* __restrict__ z,
-                                                     const double* __restrict__ q,
-                                                     const int32_t* __restrict__ m,
-                                                     const double* __restrict__ gF, int64_t n_total,
-                                                     int32_t n_items) {
-// persistent grids (fewer waves than items) stride over the items in a fixed order
-const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
-for (int32_t item = blockIdx.x * kRhoWaves + wave; item < n_items; item += gridDim.x * kRhoWaves) {
-  const RhoItem it = w.rho_items[item];
-  const SysDesc sd = w.sys[it.sys];
+template <int NPL, int KC, bool VJP, int WPB>
+__global__ __launch_bounds__(64 * WPB) void rho_f64_kernel(WsView w, const double* __restrict__ x,
+                                                          const double* __restrict__ y,
+                                                          const double* __restrict__ z,
+                                                          const double* __restrict__ q,
+                                                          const int32_t* __restrict__ m,
+                                                          const double* __restrict__ gF, int64_t n_total,
+                                                          int32_t n_items) {
+  __shared__ int32_t sched_lds[WPB == kCoopWaves ? 2 * kCoopWaves : 1];
   const int lane = threadIdx.x & 63;
-  const int first = it.tile * (64 * NPL);
-  const int cnt = min(64 * NPL, sd.n - first);
-  const double invL = 1.0 / sd.L;
+  const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+  RhoSchedule<WPB> sched(n_items, wave, sched_lds);
 
   double sx[NPL], sy[NPL], sz[NPL], qv[NPL];
   double qgx[VJP ? NPL : 1], qgy[VJP ? NPL : 1], qgz[VJP ? NPL : 1];
-#pragma unroll
-  for (int j = 0; j < NPL; ++j) {
-    const int li = j * 64 + lane;
-    if (li < cnt) {
-      const int64_t gi = sd.n_off + first + li;
-      const double vx = x[gi] * invL, vy = y[gi] * invL, vz = z[gi] * invL;
-      sx[j] = vx - floor(vx);
-      sy[j] = vy - floor(vy);
-      sz[j] = vz - floor(vz);
-      qv[j] = q[gi];
-      if (VJP) {
-        qgx[j] = qv[j] * gF[gi];
-        qgy[j] = qv[j] * gF[n_total + gi];
-        qgz[j] = qv[j] * gF[2 * n_total + gi];
-      }
-    } else {
-      sx[j] = sy[j] = sz[j] = 0.0;
-      qv[j] = 0.0;
-      if (VJP) qgx[j] = qgy[j] = qgz[j] = 0.0;
-    }
-  }
-  double* part = w.partials + 2 * sd.part_off;
-  const int32_t* mk = m + 3 * (sd.k_off + it.k0);
+  int32_t cur_sys = -1, cur_tile = -1;   // tile held in registers
 
-  const bool more_items = item + (int32_t)gridDim.x * kRhoWaves < n_items;
-  for (int kc = 0; kc < it.nk; kc += KC) {
-    remaining_priority(more_items ? 4 : (it.nk - kc + KC - 1) / KC);
-    double mx[KC], my[KC], mz[KC];
+  for (int32_t item = sched.first(); item >= 0; item = sched.next()) {
+    // the item index is wave-uniform; saying so keeps the item and its wave vectors in
+    // scalar registers and scalar loads
+    const RhoItem it = w.rho_items[__builtin_amdgcn_readfirstlane(item)];
+    const SysDesc sd = w.sys[it.sys];
+    if (it.sys != cur_sys || it.tile != cur_tile) {
+      cur_sys = it.sys;
+      cur_tile = it.tile;
+      const int first = it.tile * (64 * NPL);
+      const int cnt = min(64 * NPL, sd.n - first);
+      const double invL = 1.0 / sd.L;
 #pragma unroll
-    for (int c = 0; c < KC; ++c) {
-      const int kk = min(kc + c, it.nk - 1);
-      const int32_t a = mk[3 * kk], b = mk[3 * kk + 1], d = mk[3 * kk + 2];
-      const bool ok = kc + c < it.nk;
-      mx[c] = ok ? (double)a : 0.0;
-      my[c] = ok ? (double)b : 0.0;
-      mz[c] = ok ? (double)d : 0.0;
+      for (int j = 0; j < NPL; ++j) {
+        const int li = j * 64 + lane;
+        if (li < cnt) {
+          const int64_t gi = sd.n_off + first + li;
+          const double vx = x[gi] * invL, vy = y[gi] * invL, vz = z[gi] * invL;
+          sx[j] = vx - floor(vx);
+          sy[j] = vy - floor(vy);
+          sz[j] = vz - floor(vz);
+          qv[j] = q[gi];
+          if (VJP) {
+            qgx[j] = qv[j] * gF[gi];
+            qgy[j] = qv[j] * gF[n_total + gi];
+            qgz[j] = qv[j] * gF[2 * n_total + gi];
+          }
+        } else {
+          sx[j] = sy[j] = sz[j] = 0.0;
+          qv[j] = 0.0;
+          if (VJP) qgx[j] = qgy[j] = qgz[j] = 0.0;
+        }
+      }
     }
-    double acc[2 * KC];
-#pragma unroll
-    for (int c = 0; c < 2 * KC; ++c) acc[c] = 0.0;
-#pragma unroll
-    for (int j = 0; j < NPL; ++j) {
+    double* part = w.partials + 2 * sd.part_off;
+    const int32_t* mk = m + 3 * (sd.k_off + it.k0);
+
+    for (int kc = 0; kc < it.nk; kc += KC) {
+      sched.priority((it.nk - kc + KC - 1) / KC);
+      double mx[KC], my[KC], mz[KC];
 #pragma unroll
       for (int c = 0; c < KC; ++c) {
-        double sn, cs;
-        sincos_turns(phase_f64(mx[c], my[c], mz[c], sx[j], sy[j], sz[j]), &sn, &cs);
-        double wt = qv[j];
-        if (VJP) wt = fma(qgx[j], mx[c], fma(qgy[j], my[c], qgz[j] * mz[c]));
-        acc[c] = fma(wt, cs, acc[c]);
-        acc[KC + c] = fma(wt, sn, acc[KC + c]);
+        const int kk = min(kc + c, it.nk - 1);
+        const int32_t a = mk[3 * kk], b = mk[3 * kk + 1], d = mk[3 * kk + 2];
+        const bool ok = kc + c < it.nk;
+        mx[c] = ok ? (double)a : 0.0;
+        my[c] = ok ? (double)b : 0.0;
+        mz[c] = ok ? (double)d : 0.0;
+      }
+      double acc[2 * KC];
+#pragma unroll
+      for (int c = 0; c < 2 * KC; ++c) acc[c] = 0.0;
+#pragma unroll
+      for (int j = 0; j < NPL; ++j) {
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+          double sn, cs;
+          sincos_turns(phase_f64(mx[c], my[c], mz[c], sx[j], sy[j], sz[j]), &sn, &cs);
+          double wt = qv[j];
+          if (VJP) wt = fma(qgx[j], mx[c], fma(qgy[j], my[c], qgz[j] * mz[c]));
+          acc[c] = fma(wt, cs, acc[c]);
+          acc[KC + c] = fma(wt, sn, acc[KC + c]);
+        }
+      }
+      wave_reduce_scatter<2 * KC>(acc, lane);
+      if (lane < 2 * KC) {
+        const int vi = scatter_index(lane, Log2<2 * KC>::value);
+        const int c = vi % KC;
+        const int comp = vi / KC;
+        if (kc + c < it.nk) {
+          const int64_t kl = it.k0 + kc + c;
+          part[2 * (kl * sd.ntiles + it.tile) + comp] = acc[0];
+        }
       }
     }
-    wave_reduce_scatter<2 * KC>(acc, lane);
-    if (lane < 2 * KC) {
-      const int vi = scatter_index(lane, Log2<2 * KC>::value);
-      const int c = vi % KC;
-      const int comp = vi / KC;
-      if (kc + c < it.nk) {
-        const int64_t kl = it.k0 + kc + c;
-        part[2 * (kl * sd.ntiles + it.tile) + comp] = acc[0];
-      }
-    }
-  }
   }
 }
 
@@ -993,34 +1073,52 @@ size_t occupancy_clamp_lds(int32_t n_waves) {
   }
   if (cus <= 0) return 0;
   const int64_t per_simd = std::max<int64_t>((n_waves + 4LL * cus - 1) / (4LL * cus), 1);
-  const size_t bytes = (size_t)(lds_per_cu / per_simd) / 256 * 256;
-  return std::min<size_t>(bytes, 64 * 1024);
+  // 256 bytes below the share, which leaves room for the kernel's own static LDS
+  const int64_t bytes = (int64_t)(lds_per_cu / per_simd) / 256 * 256 - 256;
+  return (size_t)std::min<int64_t>(std::max<int64_t>(bytes, 0), 64 * 1024);
 }
 
-// Blocks of the rho-shaped passes: one wave per item (at most cap waves when cap > 0),
-// kRhoWaves waves per block.
-dim3 rho_grid(int32_t n_items, int32_t cap) {
+int num_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, v = 0;
+    cus = (hipGetDevice(&dev) == hipSuccess &&
+           hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+              ? v
+              : 256;
+  }
+  return cus;
+}
+
+// Blocks of the rho-shaped passes.  WPB = 4: one wave per item (at most cap waves when
+// cap > 0).  WPB = 16: one block per CU (fewer for small item counts, at most cap / 16).
+dim3 rho_grid(int32_t n_items, int32_t cap, int wpb) {
+  if (wpb == kCoopWaves) {
+    int64_t blocks = std::min<int64_t>(num_cus(), ((int64_t)n_items + kCoopWaves - 1) / kCoopWaves);
+    if (cap > 0) blocks = std::min<int64_t>(blocks, ((int64_t)cap + kCoopWaves - 1) / kCoopWaves);
+    return dim3((unsigned)std::max<int64_t>(blocks, 1));
+  }
   const int32_t waves = (cap > 0 && cap < n_items) ? cap : n_items;
-  return dim3((unsigned)((waves + kRhoWaves - 1) / kRhoWaves));
+  return dim3((unsigned)((waves + 3) / 4));
 }
 
-template <int NPL, int KC, bool CACHE, bool VJP, bool FPH>
+template <int NPL, int KC, bool CACHE, bool VJP, bool FPH, int WPB>
 void launch_rho_f32_t(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                       const double* z, const double* q, const int32_t* m, const float* gF,
                       hipStream_t st) {
-  const dim3 grid = rho_grid(s.n_rho_items, s.rho_grid_cap);
-  const size_t lds = s.rho_clamp ? occupancy_clamp_lds((int32_t)grid.x * kRhoWaves) : 0;
-  hipLaunchKernelGGL((rho_f32_kernel<NPL, KC, CACHE, VJP, FPH>), grid, dim3(64 * kRhoWaves), lds, st, w, x, y, z,
+  const dim3 grid = rho_grid(s.n_rho_items, s.rho_grid_cap, WPB);
+  const size_t lds = (WPB == 4 && s.rho_clamp) ? occupancy_clamp_lds((int32_t)grid.x * 4) : 0;
+  hipLaunchKernelGGL((rho_f32_kernel<NPL, KC, CACHE, VJP, FPH, WPB>), grid, dim3(64 * WPB), lds, st, w, x, y, z,
                      q, m, gF, s.n_total, s.n_rho_items);
 }
 
-template <int NPL, int KC, bool VJP>
+template <int NPL, int KC, bool VJP, int WPB>
 void launch_rho_f64_t(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                       const double* z, const double* q, const int32_t* m, const double* gF,
                       hipStream_t st) {
-  const dim3 grid = rho_grid(s.n_rho_items, s.rho_grid_cap);
-  const size_t lds = s.rho_clamp ? occupancy_clamp_lds((int32_t)grid.x * kRhoWaves) : 0;
-  hipLaunchKernelGGL((rho_f64_kernel<NPL, KC, VJP>), grid, dim3(64 * kRhoWaves), lds, st, w, x, y, z, q, m, gF,
+  const dim3 grid = rho_grid(s.n_rho_items, s.rho_grid_cap, WPB);
+  const size_t lds = (WPB == 4 && s.rho_clamp) ? occupancy_clamp_lds((int32_t)grid.x * 4) : 0;
+  hipLaunchKernelGGL((rho_f64_kernel<NPL, KC, VJP, WPB>), grid, dim3(64 * WPB), lds, st, w, x, y, z, q, m, gF,
                      s.n_total, s.n_rho_items);
 }
 
@@ -1028,10 +1126,12 @@ void launch_rho_f64_t(const LaunchShape& s, const WsView& w, const double* x, co
 template <bool CACHE, bool VJP, bool FPH>
 void tile_pass_f32(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                    const double* z, const double* q, const int32_t* m, const float* g, hipStream_t st) {
-  switch (s.rv.npl * 100 + s.rv.kc) {
-    case 1608: launch_rho_f32_t<16, 8, CACHE, VJP, FPH>(s, w, x, y, z, q, m, g, st); break;
-    case 808: launch_rho_f32_t<8, 8, CACHE, VJP, FPH>(s, w, x, y, z, q, m, g, st); break;
-    case 804: launch_rho_f32_t<8, 4, CACHE, VJP, FPH>(s, w, x, y, z, q, m, g, st); break;
+  switch (s.rv.wpb * 10000 + s.rv.npl * 100 + s.rv.kc) {
+    case 160808: launch_rho_f32_t<8, 8, CACHE, VJP, FPH, 16>(s, w, x, y, z, q, m, g, st); break;
+    case 160804: launch_rho_f32_t<8, 4, CACHE, VJP, FPH, 16>(s, w, x, y, z, q, m, g, st); break;
+    case 41608: launch_rho_f32_t<16, 8, CACHE, VJP, FPH, 4>(s, w, x, y, z, q, m, g, st); break;
+    case 40808: launch_rho_f32_t<8, 8, CACHE, VJP, FPH, 4>(s, w, x, y, z, q, m, g, st); break;
+    case 40804: launch_rho_f32_t<8, 4, CACHE, VJP, FPH, 4>(s, w, x, y, z, q, m, g, st); break;
     default: break;
   }
 }
@@ -1053,11 +1153,12 @@ void launch_tile_pass(const LaunchShape& s, const WsView& w, const double* x, co
     tile_pass_f32<false, VJP, true>(s, w, x, y, z, q, m, static_cast<const float*>(gF), st);
   } else {
     const double* g = static_cast<const double*>(gF);
-    switch (s.rv.npl * 100 + s.rv.kc) {
-      case 804: launch_rho_f64_t<8, 4, VJP>(s, w, x, y, z, q, m, g, st); break;
-      case 404: launch_rho_f64_t<4, 4, VJP>(s, w, x, y, z, q, m, g, st); break;
-      case 408: launch_rho_f64_t<4, 8, VJP>(s, w, x, y, z, q, m, g, st); break;
-      case 802: launch_rho_f64_t<8, 2, VJP>(s, w, x, y, z, q, m, g, st); break;
+    switch (s.rv.wpb * 10000 + s.rv.npl * 100 + s.rv.kc) {
+      case 160404: launch_rho_f64_t<4, 4, VJP, 16>(s, w, x, y, z, q, m, g, st); break;
+      case 40804: launch_rho_f64_t<8, 4, VJP, 4>(s, w, x, y, z, q, m, g, st); break;
+      case 40404: launch_rho_f64_t<4, 4, VJP, 4>(s, w, x, y, z, q, m, g, st); break;
+      case 40408: launch_rho_f64_t<4, 8, VJP, 4>(s, w, x, y, z, q, m, g, st); break;
+      case 40802: launch_rho_f64_t<8, 2, VJP, 4>(s, w, x, y, z, q, m, g, st); break;
       default: break;
     }
   }

@@ -88,6 +88,12 @@ def rbe_kspace_force(plan, x, y, z, q, m, w, rho, F, U, ws, stream=None):
                                   _ptr(F), _ptr(U), _ptr(ws), _stream(stream)), "rbe_kspace_force")
 
 
+def rbe_evaluate(plan, seed, stream_base, step_counter, x, y, z, q, m, w, rho, F, U, ws, stream=None):
+    check(load().rbe_evaluate(plan, seed, stream_base, _ptr(step_counter), _ptr(x), _ptr(y), _ptr(z), _ptr(q),
+                              _ptr(m), _ptr(w), _ptr(rho), _ptr(F), _ptr(U), _ptr(ws), _stream(stream)),
+          "rbe_evaluate")
+
+
 def rbe_kspace_vjp(plan, x, y, z, q, m, w, rho, gU, gF, gr, gq, ws, stream=None):
     check(load().rbe_kspace_vjp(plan, _ptr(x), _ptr(y), _ptr(z), _ptr(q), _ptr(m), _ptr(w), _ptr(rho),
                                 _ptr(gU), _ptr(gF), _ptr(gr), _ptr(gq), _ptr(ws), _stream(stream)),
@@ -273,6 +279,29 @@ class Plan:
 
     def set_grid_caps(self, rho_cap: int, force_cap: int):
         check(self.lib.rbe_plan_set_grid_caps(self.handle, rho_cap, force_cap), "rbe_plan_set_grid_caps")
+
+    def evaluate(self, x, y, z, q, seed: int, stream_base: int = 0, step_counter=None, out=None, stream=None):
+        """One whole evaluation (device sampling, rho, force and energy) enqueued without
+        synchronisation.  out: (m, w, rho, F, U) buffers to reuse, else new ones.
+        Returns (m, w, rho, F, U)."""
+        self._check_particles(x, y, z, q)
+        if out is None:
+            dev = self.device
+            out = (torch.empty((self.p_total, 3), dtype=torch.int32, device=dev),
+                   torch.empty(self.p_total, dtype=torch.float64, device=dev),
+                   torch.empty((self.p_total, 2), dtype=torch.float64, device=dev),
+                   torch.empty((3, self.n_total), dtype=self.force_dtype, device=dev),
+                   torch.empty(self.batch.B, dtype=torch.float64, device=dev))
+        m, w, rho, F, U = out
+        _dev(m, torch.int32, "m")
+        _dev(w, torch.float64, "w")
+        _dev(rho, torch.float64, "rho")
+        _dev(F, self.force_dtype, "F")
+        _dev(U, torch.float64, "U")
+        if step_counter is not None:
+            _dev(step_counter, torch.int64, "step_counter")
+        rbe_evaluate(self.handle, seed, stream_base, step_counter, x, y, z, q, m, w, rho, F, U, self.ws, stream)
+        return out
 
     def graph(self, x, y, z, q, seed: int, stream_base: int = 0, step_counter=None):
         """A captured evaluation (sample -> rho -> force) of this plan; see EvalGraph."""
