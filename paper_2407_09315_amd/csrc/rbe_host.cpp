@@ -114,10 +114,11 @@ struct rbe_plan {
   std::vector<SysDesc> sys;
   std::vector<RhoItem> rho_items;
   std::vector<ForceItem> force_items;
-  std::vector<int32_t> ksys;
+  std::vector<KRed> kred;
   std::vector<double> cdf;
+  int64_t cdf_stride = kCdfHeader;   // doubles per system table
   // workspace layout (byte offsets)
-  size_t off_sys = 0, off_rho = 0, off_force = 0, off_ksys = 0, off_cdf = 0, off_part = 0,
+  size_t off_sys = 0, off_rho = 0, off_force = 0, off_kred = 0, off_cdf = 0, off_part = 0,
          off_xy = 0, off_cache = 0, total = 0;
   size_t ws_bytes = 0;      // workspace size: the largest layout over all variants
   int64_t n_partials = 0;   // complex slots
@@ -145,7 +146,7 @@ void build_layout(rbe_plan* p) {
   p->sys.assign(p->B, SysDesc{});
   p->rho_items.clear();
   p->force_items.clear();
-  p->ksys.assign((size_t)p->p_total(), 0);
+  p->kred.assign((size_t)p->p_total(), KRed{});
   int64_t part = 0, cache = 0;
   for (int32_t b = 0; b < p->B; ++b) {
     SysDesc& s = p->sys[b];
@@ -159,7 +160,7 @@ void build_layout(rbe_plan* p) {
     part += (int64_t)s.ntiles * s.p;
     s.cache_off = cache;
     if (p->cached) cache += (int64_t)s.n * s.p;
-    for (int32_t l = 0; l < s.p; ++l) p->ksys[(size_t)(s.k_off + l)] = b;
+    for (int32_t l = 0; l < s.p; ++l) p->kred[(size_t)(s.k_off + l)] = KRed{s.part_off + (int64_t)l * s.ntiles, s.ntiles, 0};
     const int nf = std::max(1, (s.n + fchunk - 1) / fchunk);
     for (int f = 0; f < nf; ++f) {
       const int p0 = f * fchunk;
@@ -199,25 +200,41 @@ void build_layout(rbe_plan* p) {
     for (const Range& r : ranges)
       for (int32_t t = 0; t < p->sys[r.b].ntiles; ++t) p->rho_items.push_back(RhoItem{r.b, t, r.k0, r.nk});
   }
-  // sampler tables: [S][c_-M .. c_M] per system
-  p->cdf.clear();
+  // sampler tables: header (S, 2M+1, p, k_off) and c_-M .. c_M per system, fixed stride
   p->sampler_ok = true;
+  std::vector<ComponentTable> tabs((size_t)p->B);
+  int64_t max_len = 0;
   for (int32_t b = 0; b < p->B; ++b) {
     SysDesc& s = p->sys[b];
-    const ComponentTable t = component_table(p->L[b], p->alpha[b]);
+    tabs[(size_t)b] = component_table(p->L[b], p->alpha[b]);
+    const ComponentTable& t = tabs[(size_t)b];
     const double p0 = t.c[(size_t)t.M] - (t.M > 0 ? t.c[(size_t)t.M - 1] : 0.0);
     const double pz = p0 / t.c.back();
     if (pz * pz * pz > 0.5 || t.c.size() > (1u << 22)) {
       p->sampler_ok = false;
       s.cdf_len = 0;
-      s.cdf_off = (int64_t)p->cdf.size();
-      p->cdf.push_back(0.0);
       continue;
     }
-    s.cdf_off = (int64_t)p->cdf.size();
     s.cdf_len = (int32_t)t.c.size();
-    p->cdf.push_back(normalization(p->L[b], p->alpha[b]));
-    p->cdf.insert(p->cdf.end(), t.c.begin(), t.c.end());
+    max_len = std::max<int64_t>(max_len, s.cdf_len);
+  }
+  p->cdf_stride = kCdfHeader + max_len;
+  if ((int64_t)p->B * p->cdf_stride > ((int64_t)1 << 25)) {
+    // tables this large (over 256 MB in all) are not kept on the device
+    p->sampler_ok = false;
+    for (SysDesc& s : p->sys) s.cdf_len = 0;
+    p->cdf_stride = kCdfHeader;
+  }
+  p->cdf.assign((size_t)(p->B * p->cdf_stride), 0.0);
+  for (int32_t b = 0; b < p->B; ++b) {
+    const SysDesc& s = p->sys[b];
+    double* h = p->cdf.data() + (size_t)b * (size_t)p->cdf_stride;
+    h[2] = s.p;
+    h[3] = (double)s.k_off;
+    if (s.cdf_len == 0) continue;
+    h[0] = normalization(p->L[b], p->alpha[b]);
+    h[1] = s.cdf_len;
+    std::copy(tabs[(size_t)b].c.begin(), tabs[(size_t)b].c.end(), h + kCdfHeader);
   }
   p->n_partials = part;
   p->n_cache = cache;
@@ -225,7 +242,7 @@ void build_layout(rbe_plan* p) {
   p->off_sys = o;   o = align_up(o + sizeof(SysDesc) * p->sys.size());
   p->off_rho = o;   o = align_up(o + sizeof(RhoItem) * p->rho_items.size());
   p->off_force = o; o = align_up(o + sizeof(ForceItem) * p->force_items.size());
-  p->off_ksys = o;  o = align_up(o + sizeof(int32_t) * p->ksys.size());
+  p->off_kred = o;  o = align_up(o + sizeof(KRed) * p->kred.size());
   p->off_cdf = o;   o = align_up(o + sizeof(double) * p->cdf.size());
   p->off_part = o;  o = align_up(o + 2 * sizeof(double) * (size_t)p->n_partials);
   p->off_xy = o;    o = align_up(o + 2 * sizeof(double) * (size_t)p->p_total());
@@ -239,7 +256,7 @@ WsView view_of(const rbe_plan* p, void* ws) {
   w.sys = reinterpret_cast<const SysDesc*>(b + p->off_sys);
   w.rho_items = reinterpret_cast<const RhoItem*>(b + p->off_rho);
   w.force_items = reinterpret_cast<const ForceItem*>(b + p->off_force);
-  w.ksys = reinterpret_cast<const int32_t*>(b + p->off_ksys);
+  w.kred = reinterpret_cast<const KRed*>(b + p->off_kred);
   w.cdf = reinterpret_cast<const double*>(b + p->off_cdf);
   w.partials = reinterpret_cast<double*>(b + p->off_part);
   w.xy = reinterpret_cast<double*>(b + p->off_xy);
@@ -260,8 +277,7 @@ LaunchShape shape_of(const rbe_plan* p) {
   s.rho_variant = p->rho_variant;
   s.fv = kForceVariants[p->force_variant];
   s.force_variant = p->force_variant;
-  s.max_cdf_len = 0;
-  for (const SysDesc& d : p->sys) s.max_cdf_len = std::max(s.max_cdf_len, d.cdf_len);
+  s.cdf_stride = (int32_t)p->cdf_stride;
   s.rho_grid_cap = p->rho_grid_cap;
   s.rho_clamp = p->rho_clamp;
   s.force_grid_cap = p->force_grid_cap;
@@ -470,7 +486,7 @@ rbe_status rbe_plan_upload(const rbe_plan* p, void* ws, void* stream) {
       {p->off_sys, p->sys.data(), sizeof(SysDesc) * p->sys.size()},
       {p->off_rho, p->rho_items.data(), sizeof(RhoItem) * p->rho_items.size()},
       {p->off_force, p->force_items.data(), sizeof(ForceItem) * p->force_items.size()},
-      {p->off_ksys, p->ksys.data(), sizeof(int32_t) * p->ksys.size()},
+      {p->off_kred, p->kred.data(), sizeof(KRed) * p->kred.size()},
       {p->off_cdf, p->cdf.data(), sizeof(double) * p->cdf.size()},
   };
   for (const Copy& c : copies) {

@@ -20,9 +20,21 @@ struct SysDesc {
   int32_t ntiles;     // rho-pass particle tiles
   int32_t cdf_len;    // 2M+1 entries of the sampler's prefix-sum table (0: no table)
   double L;
-  int64_t cdf_off;    // first entry of the sampler table (doubles)
+  int64_t reserved;
 };
 static_assert(sizeof(SysDesc) == 64, "SysDesc layout");
+
+// Reduction descriptor of one wave vector: its tile partials are slots
+// slot .. slot + ntiles - 1 (complex) of the partial-sum region.
+struct KRed {
+  int64_t slot;
+  int32_t ntiles;
+  int32_t pad;
+};
+
+// Sampler table of system b: cdf[b * stride ...] = S, 2M+1, p, k_off (as doubles), then the
+// 2M+1 prefix sums (zero-padded to the stride), so a table's address needs no other lookup.
+constexpr int kCdfHeader = 4;
 
 // rho-pass work item: one particle tile x one range of wave vectors.
 struct RhoItem {
@@ -64,8 +76,8 @@ struct WsView {
   const SysDesc* sys;
   const RhoItem* rho_items;
   const ForceItem* force_items;
-  const int32_t* ksys;   // system of each wave vector
-  const double* cdf;     // sampler tables
+  const KRed* kred;      // reduction descriptor of each wave vector
+  const double* cdf;     // sampler tables, one per system at a fixed stride
   double* partials;      // complex partial sums (rho pass, then VJP pass B1)
   double* xy;            // P_total complex values (VJP X + iY)
   float* cache;          // (cos, sin) phase cache, FP32_MIXED + CACHED only
@@ -83,7 +95,7 @@ struct LaunchShape {
   int rho_variant;
   ForceVariant fv;
   int force_variant;
-  int32_t max_cdf_len;   // longest sampler table of the plan
+  int32_t cdf_stride;    // doubles per system in the sampler-table region
   int32_t rho_grid_cap;  // persistent-grid caps (0: one block per work item)
   int32_t rho_clamp;     // 1: cap the rho-pass blocks per CU at their even share
   int32_t force_grid_cap;

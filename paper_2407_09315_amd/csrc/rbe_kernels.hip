@@ -537,34 +537,43 @@ __global__ __launch_bounds__(64 * WPB) void rho_f64_kernel(WsView w, const doubl
 // ------------------------------------------------------------------ cross-tile reduction
 
 // One block per wave vector: out[g] = sum over the system's tiles of partial[g][tile].
-// Thread t sums tiles t, t + 256, ... in order, then a fixed tree over the block;
-// the result is optionally rotated by exp(i delta).
+// Thread t sums tiles t, t + 256, ... in order, each wave combines its lanes with a fixed
+// butterfly, and thread 0 adds the four wave sums in order; the result is optionally
+// rotated by exp(i delta).
 __global__ __launch_bounds__(kReduceBlock) void reduce_kernel(WsView w, double* __restrict__ out,
                                                               double rot_c, double rot_s) {
-  __shared__ double red_re[kReduceBlock], red_im[kReduceBlock];
+  constexpr int kWaves = kReduceBlock / 64;
+  __shared__ double wsum[2][kWaves];
   const int64_t g = blockIdx.x;
   const int tid = threadIdx.x;
-  const SysDesc sd = w.sys[w.ksys[g]];
-  const int64_t l = g - sd.k_off;
-  const double* src = w.partials + 2 * (sd.part_off + l * sd.ntiles);
+  const KRed r = w.kred[g];
+  // (re, im) pairs: 16-byte aligned (the workspace and every partial slot are)
+  const double2* src = reinterpret_cast<const double2*>(w.partials) + r.slot;
   double re = 0.0, im = 0.0;
-  for (int t = tid; t < sd.ntiles; t += kReduceBlock) {
-    re += src[2 * t];
-    im += src[2 * t + 1];
+#pragma unroll 4
+  for (int t = tid; t < r.ntiles; t += kReduceBlock) {
+    const double2 v = src[t];
+    re += v.x;
+    im += v.y;
   }
-  red_re[tid] = re;
-  red_im[tid] = im;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    re += __shfl_xor(re, o, 64);
+    im += __shfl_xor(im, o, 64);
+  }
+  if ((tid & 63) == 0) {
+    wsum[0][tid >> 6] = re;
+    wsum[1][tid >> 6] = im;
+  }
   __syncthreads();
-  for (int h = kReduceBlock / 2; h > 0; h >>= 1) {
-    if (tid < h) {
-      red_re[tid] += red_re[tid + h];
-      red_im[tid] += red_im[tid + h];
-    }
-    __syncthreads();
-  }
   if (tid == 0) {
-    re = red_re[0];
-    im = red_im[0];
+    re = wsum[0][0];
+    im = wsum[1][0];
+#pragma unroll
+    for (int i = 1; i < kWaves; ++i) {
+      re += wsum[0][i];
+      im += wsum[1][i];
+    }
     out[2 * g] = re * rot_c - im * rot_s;
     out[2 * g + 1] = re * rot_s + im * rot_c;
   }
@@ -1011,39 +1020,62 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
 // Philox key (seed + b, stream_id), counter (l, attempt, 0, 0); a zero vector is redrawn.
 constexpr int kSampleBlock = 128;
 
+// The three components' inverse-CDF searches in lockstep (the same number of halvings,
+// so their table reads overlap): for each t, the smallest j in [-M, M] with
+// t < c[j + M], or M if there is none -- the same result as inverse_cdf.
+__device__ inline void inverse_cdf3(const double* c, int32_t M, const double (&t)[3], int32_t (&v)[3]) {
+  const int32_t n = 2 * M + 1;
+  int32_t base[3] = {0, 0, 0};
+  for (int32_t len = n; len > 1;) {
+    const int32_t half = len >> 1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) base[d] = (c[base[d] + half - 1] <= t[d]) ? base[d] + half : base[d];
+    len -= half;
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int32_t idx = base[d] + (c[base[d]] <= t[d] ? 1 : 0);
+    v[d] = idx >= n ? M : idx - M;
+  }
+}
+
 __global__ __launch_bounds__(kSampleBlock) void sample_kernel(WsView w, uint64_t seed, uint64_t stream_base,
                                                               const uint64_t* __restrict__ counter,
-                                                              int32_t lds_entries, int32_t* __restrict__ m,
-                                                              double* __restrict__ wk) {
+                                                              int32_t stride, int32_t in_lds,
+                                                              int32_t* __restrict__ m, double* __restrict__ wk) {
   extern __shared__ double table[];
   const int32_t b = blockIdx.x;
   // the stream id is stream_base plus the device step counter when one is given
   const uint64_t stream_id = stream_base + (counter != nullptr ? counter[0] : 0ull);
-  const SysDesc sd = w.sys[b];
-  if (sd.p == 0) return;
-  const double S = w.cdf[sd.cdf_off];
-  const double* c = w.cdf + sd.cdf_off + 1;
-  if (sd.cdf_len <= lds_entries) {
-    for (int i = threadIdx.x; i < sd.cdf_len; i += kSampleBlock) table[i] = c[i];
+  // the table's address follows from b alone, so its load overlaps the counter's
+  const double* h = w.cdf + (int64_t)b * stride;
+  if (in_lds) {
+    for (int i = threadIdx.x; i < stride; i += kSampleBlock) table[i] = h[i];
     __syncthreads();
-    c = table;
+    h = table;
   }
-  const int32_t M = (sd.cdf_len - 1) / 2;
+  const double S = h[0];
+  const int32_t len = (int32_t)h[1];
+  const int32_t np = (int32_t)h[2];
+  const int64_t k_off = (int64_t)h[3];
+  if (np == 0 || len == 0) return;
+  const double* c = h + kCdfHeader;
+  const int32_t M = (len - 1) / 2;
   const double Z = c[2 * M];
-  for (int32_t l = threadIdx.x; l < sd.p; l += kSampleBlock) {
+  for (int32_t l = threadIdx.x; l < np; l += kSampleBlock) {
     int32_t v[3] = {0, 0, 0};
     for (int a = 0; a < kMaxAttempts; ++a) {
       U64x4 ctr = {{(uint64_t)l, (uint64_t)a, 0ull, 0ull}};
       const U64x4 r = philox4x64_10(ctr, seed + (uint64_t)b, stream_id);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) v[d] = inverse_cdf(c, M, u01_53(r.v[d]) * Z);
+      const double t[3] = {u01_53(r.v[0]) * Z, u01_53(r.v[1]) * Z, u01_53(r.v[2]) * Z};
+      inverse_cdf3(c, M, t, v);
       if (v[0] != 0 || v[1] != 0 || v[2] != 0) break;
     }
-    const int64_t g = sd.k_off + l;
+    const int64_t g = k_off + l;
     m[3 * g] = v[0];
     m[3 * g + 1] = v[1];
     m[3 * g + 2] = v[2];
-    wk[g] = (v[0] != 0 || v[1] != 0 || v[2] != 0) ? S / (double)sd.p : 0.0;
+    wk[g] = (v[0] != 0 || v[1] != 0 || v[2] != 0) ? S / (double)np : 0.0;
   }
 }
 
@@ -1304,9 +1336,11 @@ hipError_t launch_vjp(const LaunchShape& s, const WsView& w, const double* x, co
 hipError_t launch_sample(const LaunchShape& s, const WsView& w, uint64_t seed, uint64_t stream_id,
                          const uint64_t* counter, int32_t* m, double* wk, hipStream_t st) {
   if (s.p_total == 0) return hipSuccess;
-  const int32_t entries = std::min<int32_t>(s.max_cdf_len, 8192);
-  hipLaunchKernelGGL(sample_kernel, dim3((unsigned)s.B), dim3(kSampleBlock), sizeof(double) * entries, st, w, seed,
-                     stream_id, counter, entries, m, wk);
+  // tables of up to 8192 doubles (64 KB) are staged in LDS, longer ones are read in place
+  const int32_t in_lds = s.cdf_stride <= 8192 ? 1 : 0;
+  hipLaunchKernelGGL(sample_kernel, dim3((unsigned)s.B), dim3(kSampleBlock),
+                     in_lds ? sizeof(double) * (size_t)s.cdf_stride : 0, st, w, seed, stream_id, counter,
+                     s.cdf_stride, in_lds, m, wk);
   return hipGetLastError();
 }
 
