@@ -6,8 +6,9 @@ loads or calls it, and it imports nothing from the product package.
 
 Contents:
   * ``rbe_oracle.c`` -- plain FP64 definitions of rho(k), the RBE / Ewald
-    k-space force and energy, their vector-Jacobian product, and the
-    real-space + self Ewald energy, compiled with gcc into ``liboracle.so``;
+    k-space force, energy and virial tensor, their vector-Jacobian product,
+    and the real-space + self Ewald energy, compiled with gcc into
+    ``liboracle.so``;
   * ``sampler.py`` -- the exact i.i.d. wave-vector sampler, Philox4x64-10 and
     the normalisation S, in plain Python;
   * this module -- numpy wrappers.
@@ -16,7 +17,8 @@ Parity status: every function here is pinned by the ``-m "not gpu"`` tests
 against values that the paper or the mathematics fixes (closed forms,
 invariants, the rock-salt Madelung constant, an FFT of gridded charges,
 finite differences, independent autograd, a library Philox, a chi-square
-test against the exact pmf).
+test against the exact pmf; the virial against strain finite differences of
+a separate box-matrix energy).
 """
 from __future__ import annotations
 
@@ -60,6 +62,7 @@ def _load():
         lib.oracle_force_subset.argtypes = [i64, P, P, P, P, i64, P, P, d, P, i64, P, P]
         lib.oracle_vjp.argtypes = [i64, P, P, P, P, i64, P, P, d, d, P, P, P, P]
         lib.oracle_ewald_real_self.argtypes = [i64, P, P, P, P, d, d, i32, P, P]
+        lib.oracle_virial.argtypes = [i64, P, P, d, d, P, P]
         _lib = lib
     return _lib
 
@@ -134,3 +137,14 @@ def ewald_real_self(x, y, z, q, L, alpha, nmax):
     _load().oracle_ewald_real_self(q.shape[0], _ptr(x), _ptr(y), _ptr(z), _ptr(q), float(L),
                                    float(alpha), int(nmax), _ptr(ur), _ptr(us))
     return float(ur[0]), float(us[0])
+
+
+def virial(m, w, L, alpha, rho_c):
+    """k-space virial tensor (xx, yy, zz, xy, xz, yz) from a complex rho (P,)."""
+    m = np.ascontiguousarray(m, dtype=np.int32)
+    w = _f64(w)
+    rc = np.asarray(rho_c)
+    rho = np.ascontiguousarray(np.stack([rc.real, rc.imag], axis=1).reshape(-1), dtype=np.float64)
+    W = np.zeros(6)
+    _load().oracle_virial(m.shape[0], _ptr(m), _ptr(w), float(L), float(alpha), _ptr(rho), _ptr(W))
+    return W

@@ -217,6 +217,36 @@ void oracle_vjp(int64_t n, const double *x, const double *y, const double *z, co
 }
 
 /*
+ * k-space virial tensor: the negative derivative of the long-range energy term with
+ * respect to a symmetric affine strain of the box at fixed fractional coordinates
+ * (the pressure of the NPT variant the paper cites in Sec. 2.2).  With
+ * U_l = (c_l / 2) |rho_l|^2,
+ *   W_ab = sum_l U_l (delta_ab - 2 k_la k_lb (1/k_l^2 + 1/(4 alpha))).
+ * The 1/(4 alpha) part comes from the k-dependence of the Ewald kernel
+ * exp(-k^2/4 alpha); with RBE weights w_l = S/P the same sum is the importance-
+ * sampled estimate of the Ewald k-space virial.  W[6] = xx, yy, zz, xy, xz, yz.
+ */
+void oracle_virial(int64_t p, const int32_t *m, const double *w, double L, double alpha,
+                   const double *rho, double *W)
+{
+    nsum acc[6] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    static const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+    for (int64_t l = 0; l < p; ++l) {
+        double k[3];
+        wave_vector(m, l, L, k);
+        double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+        if (k2 == 0.0) continue;
+        double u = 0.5 * coef(m, l, w, L) * (rho[2 * l] * rho[2 * l] + rho[2 * l + 1] * rho[2 * l + 1]);
+        double g = 2.0 * (1.0 / k2 + 1.0 / (4.0 * alpha));
+        for (int c = 0; c < 6; ++c) {
+            double t = (ia[c] == ib[c] ? 1.0 : 0.0) - g * k[ia[c]] * k[ib[c]];
+            nsum_add(&acc[c], u * t);
+        }
+    }
+    for (int c = 0; c < 6; ++c) W[c] = nsum_get(&acc[c]);
+}
+
+/*
  * Real-space and self parts of the Ewald energy (Sec. 2.2, split energy):
  *   U_real = 1/2 sum_{i,j} sum'_{|n_d| <= nmax} q_i q_j erfc(sqrt(alpha) |r_ij + n L|) / |r_ij + n L|
  *   U_self = -sqrt(alpha / pi) sum_i q_i^2
