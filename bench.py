@@ -157,6 +157,8 @@ def main():
         log("vjp done")
         extra.update(bench_batched(torch, ri, Plan, Batch, dev, max(5, args.steps // 5)))
         log("batched done")
+        extra.update(bench_virial(torch, Plan, Batch, X, s, alpha, P, args.steps))
+        log("virial done")
 
     f32, f64 = res["fp32"], res["fp64"]
     value = terms / f32["wall_s"] / 1e9
@@ -272,6 +274,23 @@ def cpu_baseline(s, P, res):
                       "energy_rel": float(abs(r["U"] - U_ref2) / abs(U_ref2)),
                       "rho_max_over_qnorm": float(np.max(np.abs(rc - rho_ref2)) / np.sqrt(np.sum(s.q ** 2)))}
     return base, errs
+
+
+def bench_virial(torch, Plan, Batch, X, s, alpha, P, steps):
+    """Virial tensor (rbe_kspace_virial) after an FP32-mixed evaluation: mean kernel time."""
+    plan = Plan(Batch.single(s.n, P, s.L, alpha), precision="fp32_mixed")
+    m, w = plan.sample_k_device(2003, 0)
+    F, U, rho = plan.forward(*X, m, w)
+    W = plan.kspace_virial(m, w, rho)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.kspace_virial(m, w, rho, W)
+    e1.record()
+    torch.cuda.synchronize()
+    return {"virial_tensor_fp32_mixed_P100": {"us_per_call": round(e0.elapsed_time(e1) * 1e3 / steps, 2),
+                                              "W_xx_yy_zz_xy_xz_yz": [round(v, 6) for v in W[0].tolist()]}}
 
 
 def bench_vjp(torch, ri, Plan, Batch, dev, steps):

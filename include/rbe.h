@@ -213,6 +213,22 @@ rbe_status rbe_kspace_force(const rbe_plan *plan, const double *x, const double 
                             void *stream);
 
 /*
+ * k-space virial tensor of every system (the pressure term of the NPT variant the
+ * paper cites in Sec. 2.2): the negative derivative of the long-range energy
+ * term under a symmetric affine strain of the box at fixed fractional
+ * coordinates,
+ *   W_ab = sum_l U_l (delta_ab - 2 k_la k_lb (1/k_l^2 + 1/(4 alpha))),
+ *   U_l = (c_l / 2) |rho_l|^2.
+ * The 1/(4 alpha) part is the strain derivative of the Ewald kernel
+ * exp(-k^2/4 alpha); with RBE weights w = S/P the sum is the importance-sampled
+ * estimate of the Ewald k-space virial.  m, w, rho: (dev) as for
+ * rbe_kspace_force.  W: (dev) 6 FP64 values per system, in the order xx, yy,
+ * zz, xy, xz, yz.  Summed in a fixed order in FP64 for every precision.
+ */
+rbe_status rbe_kspace_virial(const rbe_plan *plan, const int32_t *m, const double *w,
+                             const double *rho, double *W, void *ws, void *stream);
+
+/*
  * Vector-Jacobian product of (U, F) (derived from the definitions above; the
  * paper has no adjoint).  Upstream gradients: gU (dev, B FP64) on U and gF
  * (dev, 3*N_total, dtype of F) on F.  Outputs (dev, dtype of F): gr

@@ -43,6 +43,7 @@ SIGNATURES = {
     "rbe_plan_set_grid_caps": (_ST, [_VP, _I32, _I32]),
     "rbe_plan_set_timing_events": (_ST, [_VP] * 5),
     "rbe_evaluate": (_ST, [_VP, _U64, _U64] + [_VP] * 12),
+    "rbe_kspace_virial": (_ST, [_VP] * 7),
     "rbe_graph_create": (_ST, [_VP, _U64, _U64] + [_VP] * 12),
     "rbe_graph_launch": (_ST, [_VP, _VP]),
     "rbe_graph_destroy": (None, [_VP]),

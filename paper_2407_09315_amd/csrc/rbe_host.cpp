@@ -155,6 +155,7 @@ void build_layout(rbe_plan* p) {
     s.n = (int32_t)(p->sys_off[b + 1] - p->sys_off[b]);
     s.p = (int32_t)(p->k_off[b + 1] - p->k_off[b]);
     s.L = p->L[b];
+    s.alpha = p->alpha[b];
     s.ntiles = (s.n + tile - 1) / tile;
     s.part_off = part;
     part += (int64_t)s.ntiles * s.p;
@@ -524,6 +525,18 @@ rbe_status rbe_kspace_force(const rbe_plan* p, const double* x, const double* y,
   hipError_t e = launch_force(shape_of(p), view_of(p, ws), x, y, z, q, m, w, rho, F, U, nullptr,
                               static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "force pass launch");
+  return RBE_OK;
+}
+
+rbe_status rbe_kspace_virial(const rbe_plan* p, const int32_t* m, const double* w, const double* rho, double* W,
+                             void* ws, void* stream) {
+  rbe_status st = check_common(p, ws);
+  if (st != RBE_OK) return st;
+  const int64_t P = p->p_total();
+  if (!need(m, P) || !need(w, P) || !need(rho, P)) return fail(RBE_EINVAL, "NULL m, w or rho array");
+  if (W == nullptr) return fail(RBE_EINVAL, "W is NULL");
+  hipError_t e = launch_virial(shape_of(p), view_of(p, ws), m, w, rho, W, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "virial launch");
   return RBE_OK;
 }
 

@@ -20,7 +20,7 @@ struct SysDesc {
   int32_t ntiles;     // rho-pass particle tiles
   int32_t cdf_len;    // 2M+1 entries of the sampler's prefix-sum table (0: no table)
   double L;
-  int64_t reserved;
+  double alpha;       // Ewald splitting parameter (virial)
 };
 static_assert(sizeof(SysDesc) == 64, "SysDesc layout");
 
@@ -116,5 +116,7 @@ hipError_t launch_vjp(const LaunchShape& s, const WsView& w, const double* x, co
                       hipStream_t st);
 hipError_t launch_sample(const LaunchShape& s, const WsView& w, uint64_t seed, uint64_t stream_id,
                          const uint64_t* counter, int32_t* m, double* wk, hipStream_t st);
+hipError_t launch_virial(const LaunchShape& s, const WsView& w, const int32_t* m, const double* wk,
+                         const double* rho, double* W, hipStream_t st);
 
 }  // namespace rbe

@@ -579,6 +579,55 @@ __global__ __launch_bounds__(kReduceBlock) void reduce_kernel(WsView w, double* 
   }
 }
 
+// ------------------------------------------------------------------ virial
+
+// k-space virial tensor of system b (one block per system), the negative derivative of
+// the long-range energy term under a symmetric strain at fixed fractional coordinates:
+//   W_ab = sum_l U_l (delta_ab - 2 k_la k_lb (1/k_l^2 + 1/(4 alpha))),  U_l = (c_l/2)|rho_l|^2.
+// The 1/(4 alpha) part is the strain derivative of the Ewald kernel exp(-k^2/4 alpha); with
+// RBE weights the sum is the importance-sampled estimate of the Ewald virial.  Thread t
+// sums k = t, t + 256, ... in order, then a fixed tree per component; W[6b ..] = xx, yy,
+// zz, xy, xz, yz.
+__global__ __launch_bounds__(kReduceBlock) void virial_kernel(WsView w, const int32_t* __restrict__ m,
+                                                              const double* __restrict__ wk,
+                                                              const double* __restrict__ rho,
+                                                              double* __restrict__ W) {
+  __shared__ double red[6][kReduceBlock];
+  const SysDesc sd = w.sys[blockIdx.x];
+  const int tid = threadIdx.x;
+  const double kscale = kTwoPi / sd.L;
+  const double vol = sd.L * sd.L * sd.L;
+  const double g4 = 1.0 / (4.0 * sd.alpha);
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int l = tid; l < sd.p; l += kReduceBlock) {
+    const int64_t g = sd.k_off + l;
+    const double kx = kscale * m[3 * g], ky = kscale * m[3 * g + 1], kz = kscale * m[3 * g + 2];
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    if (k2 > 0.0) {
+      const double c = wk[g] * kFourPi / (vol * k2);
+      const double u = 0.5 * c * (rho[2 * g] * rho[2 * g] + rho[2 * g + 1] * rho[2 * g + 1]);
+      const double f = 2.0 * (1.0 / k2 + g4);
+      acc[0] += u * (1.0 - f * kx * kx);
+      acc[1] += u * (1.0 - f * ky * ky);
+      acc[2] += u * (1.0 - f * kz * kz);
+      acc[3] -= u * f * kx * ky;
+      acc[4] -= u * f * kx * kz;
+      acc[5] -= u * f * ky * kz;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) red[c][tid] = acc[c];
+  __syncthreads();
+  for (int h = kReduceBlock / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) red[c][tid] += red[c][tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid < 6) W[6 * (int64_t)blockIdx.x + tid] = red[tid][0];
+}
+
 // ------------------------------------------------------------------ energy helper
 
 // Fixed-order block sum of one double per thread; thread 0 gets the total.
@@ -1341,6 +1390,13 @@ hipError_t launch_sample(const LaunchShape& s, const WsView& w, uint64_t seed, u
   hipLaunchKernelGGL(sample_kernel, dim3((unsigned)s.B), dim3(kSampleBlock),
                      in_lds ? sizeof(double) * (size_t)s.cdf_stride : 0, st, w, seed, stream_id, counter,
                      s.cdf_stride, in_lds, m, wk);
+  return hipGetLastError();
+}
+
+hipError_t launch_virial(const LaunchShape& s, const WsView& w, const int32_t* m, const double* wk,
+                         const double* rho, double* W, hipStream_t st) {
+  if (s.B == 0) return hipSuccess;
+  hipLaunchKernelGGL(virial_kernel, dim3((unsigned)s.B), dim3(kReduceBlock), 0, st, w, m, wk, rho, W);
   return hipGetLastError();
 }
 

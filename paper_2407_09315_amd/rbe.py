@@ -94,6 +94,11 @@ def rbe_evaluate(plan, seed, stream_base, step_counter, x, y, z, q, m, w, rho, F
           "rbe_evaluate")
 
 
+def rbe_kspace_virial(plan, m, w, rho, W, ws, stream=None):
+    check(load().rbe_kspace_virial(plan, _ptr(m), _ptr(w), _ptr(rho), _ptr(W), _ptr(ws), _stream(stream)),
+          "rbe_kspace_virial")
+
+
 def rbe_kspace_vjp(plan, x, y, z, q, m, w, rho, gU, gF, gr, gq, ws, stream=None):
     check(load().rbe_kspace_vjp(plan, _ptr(x), _ptr(y), _ptr(z), _ptr(q), _ptr(m), _ptr(w), _ptr(rho),
                                 _ptr(gU), _ptr(gF), _ptr(gr), _ptr(gq), _ptr(ws), _stream(stream)),
@@ -258,6 +263,16 @@ class Plan:
         rho = self.structure_factor(x, y, z, q, m, stream=stream)
         F, U = self.kspace_force(x, y, z, q, m, w, rho, stream=stream)
         return F, U, rho
+
+    def kspace_virial(self, m, w, rho, W=None, stream=None):
+        """Virial tensor per system, (B, 6) FP64: xx, yy, zz, xy, xz, yz."""
+        self._check_k(m, w)
+        _dev(rho, torch.float64, "rho")
+        if W is None:
+            W = torch.empty((self.batch.B, 6), dtype=torch.float64, device=self.device)
+        _dev(W, torch.float64, "W")
+        rbe_kspace_virial(self.handle, m, w, rho, W, self.ws, stream)
+        return W
 
     def kspace_vjp(self, x, y, z, q, m, w, rho, gU, gF, gr=None, gq=None, stream=None):
         self._check_particles(x, y, z, q)
