@@ -10,11 +10,12 @@ G(particle*k)/s (N * P terms per evaluation); the FP64 form, the phase-cache
 variant, P = 200, the adjoint and the batched 128-replica form are timed
 beside it and reported in the same JSON line.
 
-roofline: VALU issue slots.  Algorithmic work per (particle, k) term, per
-kernel: rho pass 5 FMA-class ops + sin + cos; force pass 8 FMA-class ops +
-sin + cos.  On gfx950 v_sin_f32 / v_cos_f32 issue at half rate (2 slots,
-measured), other VALU ops at 1 slot.  Peak = 256 CU x 64 lanes x 2.4 GHz =
-39.32e12 lane-slots/s (packed FP32 is not used).
+roofline: FP32 vector arithmetic.  Peak = 256 CU x 128 FMA lanes x 2 FLOP x
+2.4 GHz = 157.3 TFLOP/s.  Algorithmic work per (particle, k) term in FP32 FMA
+issue-equivalents (measured rates: FP32 FMA/mul/add 1, sin or cos 4): rho pass
+phase 3 + sin + cos + 2 FMAs = 13; force pass phase 3 + sin + cos + 5 = 16;
+two FLOP each.  achieved = FLOP-eq x N * P / kernel time (HIP events around
+the dominant pass's kernel on its launch stream).
 
 cpu_baseline: the FP64 oracle (plain C, OpenMP over independent outputs) on
 the same box, the same system and the same wave vectors, repeated for about
@@ -33,9 +34,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_SLOTS = 256 * 64 * 2.4e9          # VALU lane-slots per second
-SLOTS_RHO = 5 + 2 * 2                  # per term: 5 FMA-class + sin + cos (2 slots each)
-SLOTS_FORCE = 8 + 2 * 2
+# FP32 vector peak of MI355X: 256 CUs x 128 FMA lanes x 2 FLOP x 2.4 GHz = 157.3 TFLOP/s.
+PEAK_FLOP = 256 * 128 * 2 * 2.4e9
+# Algorithmic work per (particle, wave vector) term in FP32 FMA issue-equivalents: an FP32
+# FMA/mul/add is 1, sin or cos 4 (quarter rate, measured).  rho: phase 3 + sin + cos +
+# 2 accumulating FMAs = 13; force: phase 3 + sin + cos + Im' 2 + 3 FMAs = 16.  x 2 FLOP each.
+FLOP_RHO = 2 * (3 + 4 + 4 + 2)
+FLOP_FORCE = 2 * (3 + 4 + 4 + 2 + 3)
 
 
 def parse():
@@ -164,9 +169,9 @@ def main():
     value = terms / f32["wall_s"] / 1e9
     dom = "rho" if f32["t_rho_s"] >= f32["t_force_s"] else "force"
     t_dom = f32["t_rho_s"] if dom == "rho" else f32["t_force_s"]
-    slots = SLOTS_RHO if dom == "rho" else SLOTS_FORCE
-    achieved = slots * terms / t_dom / 1e12
-    peak = PEAK_SLOTS / 1e12
+    flop = FLOP_RHO if dom == "rho" else FLOP_FORCE
+    achieved = flop * terms / t_dom / 1e12
+    peak = PEAK_FLOP / 1e12
     out = {
         "metric": "RBE force G(particle·k)/s & ms/eval at 1M, FP32-mixed vs FP64 at stated err",
         "value": round(value, 3),
@@ -196,10 +201,14 @@ def main():
         "fp32_kernels_ms": {"rho_kernel": round(f32["t_rho_s"] * 1e3, 4), "force_kernel": round(f32["t_force_s"] * 1e3, 4),
                             "tiles": f32["tiles"]},
         "roofline": {"bound": "alu", "kernel": "rho_f32_kernel" if dom == "rho" else "force_f32_kernel",
-                     "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
+                     "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4),
                      "traffic": traffic_from_profile("rho_f32_kernel" if dom == "rho" else "force_f32_kernel"),
-                     "ops_per_term": slots, "terms_per_launch": terms},
+                     "flop_equivalents_per_term": flop, "terms_per_launch": terms,
+                     "other_pass": {"kernel": "force_f32_kernel" if dom == "rho" else "rho_f32_kernel",
+                                    "frac": round((FLOP_FORCE if dom == "rho" else FLOP_RHO) * terms /
+                                                  (f32["t_force_s"] if dom == "rho" else f32["t_rho_s"]) / PEAK_FLOP, 4)},
+                     "whole_evaluation_frac": round((FLOP_RHO + FLOP_FORCE) * terms / f32["wall_s"] / PEAK_FLOP, 4)},
         "extra": extra,
     }
     if not args.quick and not args.no_cpu:

@@ -1,7 +1,9 @@
-// VALU issue-rate microbenchmark for gfx950: the rates the RBE kernels' roofline uses.
-// Each kernel runs 8 independent dependency chains per lane of one instruction kind
-// (inline VALU asm where the compiler would otherwise rewrite the operation) on 32 waves
-// per CU, and reports lane-ops per second as a fraction of one op per lane per clock.
+// VALU issue-rate microbenchmark for gfx950: the per-instruction costs the RBE kernels'
+// roofline uses.  Each kernel runs 16 independent streams per lane of one instruction
+// (inline VALU asm with VGPR operands, so the compiler cannot rewrite it) on 8 waves per
+// SIMD, long enough (several ms) for event timing.  It reports lane-ops per CU per clock
+// at the 2.4 GHz peak clock and at the clock the waves themselves measured
+// (s_memtime against the 100 MHz s_memrealtime over each wave's loop).
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -16,104 +18,153 @@
     }                                                                                    \
   } while (0)
 
-constexpr int kIter = 512;
+constexpr int kIter = 2048;
+constexpr int kStreams = 16;
+constexpr int kOps = 15;
+
+// ops per stream step and their names
+const char* kNames[kOps] = {"v_fma_f32", "v_fmac_f32", "v_add_f32", "v_mul_f32", "v_mul_lo_u32",
+                            "v_add3_u32", "v_alignbit_b32", "v_cvt_f32_i32", "v_sin_f32", "v_cos_f32",
+                            "v_fma_f64", "v_rndne_f64", "v_sin_f32 + 4 v_fma_f32", "v_sin_f32 + 4 v_mul_lo_u32",
+                            "v_sin_f32 + v_cos_f32 + 8 v_fma_f32"};
+const int kInstr[kOps] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 5, 5, 10};
 
 template <int OP>
-__global__ __launch_bounds__(256) void rate_kernel(float* outf, double* outd, int* outi, float a, float b, int ia,
-                                                   int ib, double da, double db) {
+__global__ __launch_bounds__(256) void rate_kernel(float* out, unsigned long long* clk, int n_out) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  float x[8];
-  int y[8];
-  double z[8];
-  for (int j = 0; j < 8; ++j) {
-    x[j] = 0.001f * (tid % 7 + j);
+  float x[kStreams], a = 1.0001f, b = 1e-4f;
+  uint32_t y[kStreams], ia = 3, ib = 5;
+  double z[kStreams], da = 1.0000001, db = 1e-7;
+  for (int j = 0; j < kStreams; ++j) {
+    x[j] = 1e-3f * (tid % 7 + j);
     y[j] = tid + j;
-    z[j] = 0.001 * (tid % 5 + j);
+    z[j] = 1e-3 * (tid % 5 + j);
   }
+  const unsigned long long t0 = __builtin_readcyclecounter();
+  const unsigned long long r0 = __builtin_amdgcn_s_memrealtime();
   for (int it = 0; it < kIter; ++it) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      if (OP == 0) x[j] = __builtin_amdgcn_sinf(x[j]);
-      if (OP == 1) x[j] = __builtin_amdgcn_cosf(x[j]);
-      if (OP == 2) x[j] = fmaf(x[j], a, b);
-      if (OP == 3) asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(y[j]) : "v"(ia));
-      if (OP == 4) asm volatile("v_add3_u32 %0, %0, %1, %2" : "+v"(y[j]) : "v"(ia), "v"(ib));
-      if (OP == 5) asm volatile("v_alignbit_b32 %0, %1, %0, 9" : "+v"(y[j]) : "v"(ib));
-      if (OP == 6) z[j] = fma(z[j], da, db);
-      if (OP == 7) asm volatile("v_rndne_f64 %0, %0" : "+v"(z[j]));
-      if (OP == 8) {   // one sin next to four full-rate integer ops: co-issue check
-        x[j] = __builtin_amdgcn_sinf(x[j]);
-        asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(y[j]) : "v"(ia));
-        asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(y[j]) : "v"(ib));
-        asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(y[j]) : "v"(ia));
-        asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(y[j]) : "v"(ib));
+    for (int j = 0; j < kStreams; ++j) {
+      if (OP == 0) asm volatile("v_fma_f32 %0, %0, %1, %2" : "+v"(x[j]) : "v"(a), "v"(b));
+      if (OP == 1) asm volatile("v_fmac_f32 %0, %1, %2" : "+v"(x[j]) : "v"(a), "v"(b));
+      if (OP == 2) asm volatile("v_add_f32 %0, %0, %1" : "+v"(x[j]) : "v"(b));
+      if (OP == 3) asm volatile("v_mul_f32 %0, %0, %1" : "+v"(x[j]) : "v"(a));
+      if (OP == 4) asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(y[j]) : "v"(ia));
+      if (OP == 5) asm volatile("v_add3_u32 %0, %0, %1, %2" : "+v"(y[j]) : "v"(ia), "v"(ib));
+      if (OP == 6) asm volatile("v_alignbit_b32 %0, %1, %0, 9" : "+v"(y[j]) : "v"(ib));
+      if (OP == 7) asm volatile("v_cvt_f32_i32 %0, %1" : "=v"(x[j]) : "v"(y[j]));
+      if (OP == 8) asm volatile("v_sin_f32 %0, %0" : "+v"(x[j]));
+      if (OP == 9) asm volatile("v_cos_f32 %0, %0" : "+v"(x[j]));
+      if (OP == 10) asm volatile("v_fma_f64 %0, %0, %1, %2" : "+v"(z[j]) : "v"(da), "v"(db));
+      if (OP == 11) asm volatile("v_rndne_f64 %0, %0" : "+v"(z[j]));
+      if (OP == 12) {
+        asm volatile("v_sin_f32 %0, %0" : "+v"(x[j]));
+        asm volatile("v_fma_f32 %0, %0, %1, %2\n v_fma_f32 %0, %0, %1, %2\n v_fma_f32 %0, %0, %1, %2\n v_fma_f32 %0, %0, %1, %2"
+                     : "+v"(x[(j + 8) % kStreams]) : "v"(a), "v"(b));
+      }
+      if (OP == 13) {
+        asm volatile("v_sin_f32 %0, %0" : "+v"(x[j]));
+        asm volatile("v_mul_lo_u32 %0, %0, %1\n v_mul_lo_u32 %0, %0, %1\n v_mul_lo_u32 %0, %0, %1\n v_mul_lo_u32 %0, %0, %1"
+                     : "+v"(y[j]) : "v"(ia));
+      }
+      if (OP == 14) {
+        asm volatile("v_sin_f32 %0, %0" : "+v"(x[j]));
+        asm volatile("v_cos_f32 %0, %0" : "+v"(x[(j + 4) % kStreams]));
+        asm volatile("v_fma_f32 %0, %0, %1, %2\n v_fma_f32 %0, %0, %1, %2\n v_fma_f32 %0, %0, %1, %2\n v_fma_f32 %0, %0, %1, %2"
+                     : "+v"(x[(j + 8) % kStreams]) : "v"(a), "v"(b));
+        asm volatile("v_fma_f32 %0, %0, %1, %2\n v_fma_f32 %0, %0, %1, %2\n v_fma_f32 %0, %0, %1, %2\n v_fma_f32 %0, %0, %1, %2"
+                     : "+v"(x[(j + 12) % kStreams]) : "v"(a), "v"(b));
       }
     }
   }
+  const unsigned long long t1 = __builtin_readcyclecounter();
+  const unsigned long long r1 = __builtin_amdgcn_s_memrealtime();
   float sx = 0;
-  int sy = 0;
+  uint32_t sy = 0;
   double sz = 0;
-  for (int j = 0; j < 8; ++j) {
+  for (int j = 0; j < kStreams; ++j) {
     sx += x[j];
     sy += y[j];
     sz += z[j];
   }
-  if (sx == 1234.5f) outf[tid] = sx;
-  if (sy == 123457) outi[tid] = sy;
-  if (sz == 1234.5) outd[tid] = sz;
+  if ((sx == 1234.5f || sy == 123457u || sz == 1234.5) && tid < n_out) out[tid] = sx;
+  // one (cycles, realtime ticks) pair per wave
+  const int wave = tid >> 6;
+  if ((threadIdx.x & 63) == 0 && 2 * wave + 1 < n_out) {
+    clk[2 * wave] = t1 - t0;
+    clk[2 * wave + 1] = r1 - r0;
+  }
 }
 
 template <int OP>
-float time_op(int blocks, float* f, double* d, int* i) {
+void time_op(int blocks, int lds, float* f, unsigned long long* clk, int n_out, unsigned long long* h, float* ms,
+             double* ghz) {
   hipEvent_t e0, e1;
   CHECK(hipEventCreate(&e0));
   CHECK(hipEventCreate(&e1));
-  hipLaunchKernelGGL(rate_kernel<OP>, dim3(blocks), dim3(256), 0, 0, f, d, i, 1.0001f, 0.0001f, 3, 5, 1.0000001, 1e-7);
+  hipLaunchKernelGGL(rate_kernel<OP>, dim3(blocks), dim3(256), lds, 0, f, clk, n_out);
   CHECK(hipDeviceSynchronize());
   CHECK(hipEventRecord(e0));
-  for (int r = 0; r < 5; ++r)
-    hipLaunchKernelGGL(rate_kernel<OP>, dim3(blocks), dim3(256), 0, 0, f, d, i, 1.0001f, 0.0001f, 3, 5, 1.0000001, 1e-7);
+  for (int r = 0; r < 3; ++r) hipLaunchKernelGGL(rate_kernel<OP>, dim3(blocks), dim3(256), lds, 0, f, clk, n_out);
   CHECK(hipEventRecord(e1));
   CHECK(hipEventSynchronize(e1));
-  float ms;
-  CHECK(hipEventElapsedTime(&ms, e0, e1));
+  CHECK(hipEventElapsedTime(ms, e0, e1));
+  *ms /= 3;
+  const int waves = blocks * 4;
+  CHECK(hipMemcpy(h, clk, sizeof(unsigned long long) * 2 * waves, hipMemcpyDeviceToHost));
+  double c = 0, r = 0;
+  for (int i = 0; i < waves; ++i) {
+    c += (double)h[2 * i];
+    r += (double)h[2 * i + 1];
+  }
+  *ghz = c / (r * 10.0);   // cycles per 10 ns tick of the 100 MHz real-time counter
   CHECK(hipEventDestroy(e0));
   CHECK(hipEventDestroy(e1));
-  return ms / 5;
 }
 
 int main() {
   hipDeviceProp_t prop;
   CHECK(hipGetDeviceProperties(&prop, 0));
-  std::printf("device %s, %d CUs, %d kHz\n", prop.gcnArchName, prop.multiProcessorCount, prop.clockRate);
-  const int blocks = prop.multiProcessorCount * 32;
-  const size_t nt = (size_t)blocks * 256;
+  const int cus = prop.multiProcessorCount;
+  std::printf("device %s, %d CUs, %d kHz\n", prop.gcnArchName, cus, prop.clockRate);
+  const int wps = 8;                       // waves per SIMD
+  const int blocks = cus * wps;            // 256-thread blocks: one wave per SIMD each
+  const int lds = 160 * 1024 / wps - 1024; // caps the blocks per CU at wps
+  const int n_out = blocks * 256;
   float* f;
-  double* d;
-  int* ii;
-  CHECK(hipMalloc(&f, nt * 4));
-  CHECK(hipMalloc(&d, nt * 8));
-  CHECK(hipMalloc(&ii, nt * 4));
-  const double lane_iters = (double)nt * kIter * 8;
-  const double peak = (double)prop.multiProcessorCount * 64 * (prop.clockRate * 1e3);
-  const char* names[] = {"v_sin_f32", "v_cos_f32", "v_fma_f32", "v_mul_lo_u32", "v_add3_u32",
-                         "v_alignbit_b32", "v_fma_f64", "v_rndne_f64", "v_sin_f32 + 4 v_mul_lo_u32"};
-  float t[9];
-  t[0] = time_op<0>(blocks, f, d, ii);
-  t[1] = time_op<1>(blocks, f, d, ii);
-  t[2] = time_op<2>(blocks, f, d, ii);
-  t[3] = time_op<3>(blocks, f, d, ii);
-  t[4] = time_op<4>(blocks, f, d, ii);
-  t[5] = time_op<5>(blocks, f, d, ii);
-  t[6] = time_op<6>(blocks, f, d, ii);
-  t[7] = time_op<7>(blocks, f, d, ii);
-  t[8] = time_op<8>(blocks, f, d, ii);
-  std::printf("%-28s %10s %16s %12s\n", "instruction", "ms", "lane-iters/s", "of 1/lane/clk");
-  for (int k = 0; k < 9; ++k)
-    std::printf("%-28s %10.3f %16.4e %12.3f\n", names[k], t[k], lane_iters / (t[k] * 1e-3),
-                lane_iters / (t[k] * 1e-3) / peak);
+  unsigned long long* clk;
+  CHECK(hipMalloc(&f, sizeof(float) * (size_t)n_out));
+  CHECK(hipMalloc(&clk, sizeof(unsigned long long) * (size_t)n_out));
+  unsigned long long* h = (unsigned long long*)std::malloc(sizeof(unsigned long long) * (size_t)n_out);
+  float ms[kOps];
+  double ghz[kOps];
+  time_op<0>(blocks, lds, f, clk, n_out, h, &ms[0], &ghz[0]);
+  time_op<1>(blocks, lds, f, clk, n_out, h, &ms[1], &ghz[1]);
+  time_op<2>(blocks, lds, f, clk, n_out, h, &ms[2], &ghz[2]);
+  time_op<3>(blocks, lds, f, clk, n_out, h, &ms[3], &ghz[3]);
+  time_op<4>(blocks, lds, f, clk, n_out, h, &ms[4], &ghz[4]);
+  time_op<5>(blocks, lds, f, clk, n_out, h, &ms[5], &ghz[5]);
+  time_op<6>(blocks, lds, f, clk, n_out, h, &ms[6], &ghz[6]);
+  time_op<7>(blocks, lds, f, clk, n_out, h, &ms[7], &ghz[7]);
+  time_op<8>(blocks, lds, f, clk, n_out, h, &ms[8], &ghz[8]);
+  time_op<9>(blocks, lds, f, clk, n_out, h, &ms[9], &ghz[9]);
+  time_op<10>(blocks, lds, f, clk, n_out, h, &ms[10], &ghz[10]);
+  time_op<11>(blocks, lds, f, clk, n_out, h, &ms[11], &ghz[11]);
+  time_op<12>(blocks, lds, f, clk, n_out, h, &ms[12], &ghz[12]);
+  time_op<13>(blocks, lds, f, clk, n_out, h, &ms[13], &ghz[13]);
+  time_op<14>(blocks, lds, f, clk, n_out, h, &ms[14], &ghz[14]);
+  std::printf("%d waves per SIMD, %d independent streams per lane, %d steps\n", wps, kStreams, kIter);
+  std::printf("%-36s %8s %8s %14s %14s %12s\n", "instruction (per step)", "ms", "GHz", "ops/CU/clk@2.4", "ops/CU/clk@own",
+              "cyc/wave64");
+  for (int k = 0; k < kOps; ++k) {
+    const double ops = (double)n_out * kIter * kStreams * kInstr[k];
+    const double per_cu_clk_peak = ops / (ms[k] * 1e-3) / cus / 2.4e9;
+    const double per_cu_clk_own = ops / (ms[k] * 1e-3) / cus / (ghz[k] * 1e9);
+    std::printf("%-36s %8.3f %8.3f %14.1f %14.1f %12.2f\n", kNames[k], ms[k], ghz[k], per_cu_clk_peak, per_cu_clk_own,
+                4.0 * 64.0 / per_cu_clk_own);
+  }
+  std::free(h);
   CHECK(hipFree(f));
-  CHECK(hipFree(d));
-  CHECK(hipFree(ii));
+  CHECK(hipFree(clk));
   return 0;
 }
