@@ -20,14 +20,15 @@
 
 constexpr int kIter = 2048;
 constexpr int kStreams = 16;
-constexpr int kOps = 15;
+constexpr int kOps = 21;
 
 // ops per stream step and their names
 const char* kNames[kOps] = {"v_fma_f32", "v_fmac_f32", "v_add_f32", "v_mul_f32", "v_mul_lo_u32",
                             "v_add3_u32", "v_alignbit_b32", "v_cvt_f32_i32", "v_sin_f32", "v_cos_f32",
                             "v_fma_f64", "v_rndne_f64", "v_sin_f32 + 4 v_fma_f32", "v_sin_f32 + 4 v_mul_lo_u32",
-                            "v_sin_f32 + v_cos_f32 + 8 v_fma_f32"};
-const int kInstr[kOps] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 5, 5, 10};
+                            "v_sin_f32 + v_cos_f32 + 8 v_fma_f32", "v_mul_u32_u24", "v_mad_u32_u24",
+                            "v_rndne_f32", "v_fract_f32", "v_cvt_f32_u32", "v_xad_u32"};
+const int kInstr[kOps] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 5, 5, 10, 1, 1, 1, 1, 1, 1};
 
 template <int OP>
 __global__ __launch_bounds__(256) void rate_kernel(float* out, unsigned long long* clk, int n_out) {
@@ -67,6 +68,12 @@ __global__ __launch_bounds__(256) void rate_kernel(float* out, unsigned long lon
         asm volatile("v_mul_lo_u32 %0, %0, %1\n v_mul_lo_u32 %0, %0, %1\n v_mul_lo_u32 %0, %0, %1\n v_mul_lo_u32 %0, %0, %1"
                      : "+v"(y[j]) : "v"(ia));
       }
+      if (OP == 15) asm volatile("v_mul_u32_u24 %0, %0, %1" : "+v"(y[j]) : "v"(ia));
+      if (OP == 16) asm volatile("v_mad_u32_u24 %0, %0, %1, %2" : "+v"(y[j]) : "v"(ia), "v"(ib));
+      if (OP == 17) asm volatile("v_rndne_f32 %0, %0" : "+v"(x[j]));
+      if (OP == 18) asm volatile("v_fract_f32 %0, %0" : "+v"(x[j]));
+      if (OP == 19) asm volatile("v_cvt_f32_u32 %0, %1" : "=v"(x[j]) : "v"(y[j]));
+      if (OP == 20) asm volatile("v_xad_u32 %0, %0, %1, %2" : "+v"(y[j]) : "v"(ia), "v"(ib));
       if (OP == 14) {
         asm volatile("v_sin_f32 %0, %0" : "+v"(x[j]));
         asm volatile("v_cos_f32 %0, %0" : "+v"(x[(j + 4) % kStreams]));
@@ -153,6 +160,12 @@ int main() {
   time_op<12>(blocks, lds, f, clk, n_out, h, &ms[12], &ghz[12]);
   time_op<13>(blocks, lds, f, clk, n_out, h, &ms[13], &ghz[13]);
   time_op<14>(blocks, lds, f, clk, n_out, h, &ms[14], &ghz[14]);
+  time_op<15>(blocks, lds, f, clk, n_out, h, &ms[15], &ghz[15]);
+  time_op<16>(blocks, lds, f, clk, n_out, h, &ms[16], &ghz[16]);
+  time_op<17>(blocks, lds, f, clk, n_out, h, &ms[17], &ghz[17]);
+  time_op<18>(blocks, lds, f, clk, n_out, h, &ms[18], &ghz[18]);
+  time_op<19>(blocks, lds, f, clk, n_out, h, &ms[19], &ghz[19]);
+  time_op<20>(blocks, lds, f, clk, n_out, h, &ms[20], &ghz[20]);
   std::printf("%d waves per SIMD, %d independent streams per lane, %d steps\n", wps, kStreams, kIter);
   std::printf("%-36s %8s %8s %14s %14s %12s\n", "instruction (per step)", "ms", "GHz", "ops/CU/clk@2.4", "ops/CU/clk@own",
               "cyc/wave64");
