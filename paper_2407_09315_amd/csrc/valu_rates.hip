@@ -20,15 +20,18 @@
 
 constexpr int kIter = 2048;
 constexpr int kStreams = 16;
-constexpr int kOps = 21;
+constexpr int kOps = 26;
 
 // ops per stream step and their names
 const char* kNames[kOps] = {"v_fma_f32", "v_fmac_f32", "v_add_f32", "v_mul_f32", "v_mul_lo_u32",
                             "v_add3_u32", "v_alignbit_b32", "v_cvt_f32_i32", "v_sin_f32", "v_cos_f32",
-                            "v_fma_f64", "v_rndne_f64", "v_sin_f32 + 4 v_fma_f32", "v_sin_f32 + 4 v_mul_lo_u32",
-                            "v_sin_f32 + v_cos_f32 + 8 v_fma_f32", "v_mul_u32_u24", "v_mad_u32_u24",
-                            "v_rndne_f32", "v_fract_f32", "v_cvt_f32_u32", "v_xad_u32"};
-const int kInstr[kOps] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 5, 5, 10, 1, 1, 1, 1, 1, 1};
+                            "v_fma_f64", "v_rndne_f64", "v_sin_f32 + 4 dependent v_fma_f32", "v_sin_f32 + 4 dependent v_mul_lo_u32",
+                            "v_sin_f32 + v_cos_f32 + 2 x 4 dependent v_fma_f32", "v_mul_u32_u24", "v_mad_u32_u24",
+                            "v_rndne_f32", "v_fract_f32", "v_cvt_f32_u32", "v_xad_u32",
+                            "v_sin_f32 + 4 independent v_fma_f32", "4 v_mul_lo_u32 then 4 v_fma_f32",
+                            "v_sin_f32 + 4 v_mul_lo_u32 + 4 v_fma_f32", "force term: sin cos 5 int 5 fma",
+                            "rho term: sin cos 5 int 2 fma"};
+const int kInstr[kOps] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 5, 5, 10, 1, 1, 1, 1, 1, 1, 5, 8, 9, 12, 9};
 
 template <int OP>
 __global__ __launch_bounds__(256) void rate_kernel(float* out, unsigned long long* clk, int n_out) {
@@ -74,6 +77,47 @@ __global__ __launch_bounds__(256) void rate_kernel(float* out, unsigned long lon
       if (OP == 18) asm volatile("v_fract_f32 %0, %0" : "+v"(x[j]));
       if (OP == 19) asm volatile("v_cvt_f32_u32 %0, %1" : "=v"(x[j]) : "v"(y[j]));
       if (OP == 20) asm volatile("v_xad_u32 %0, %0, %1, %2" : "+v"(y[j]) : "v"(ia), "v"(ib));
+      // mixes with independent FP32 operands: f[] streams 4 apart, so no FMA waits on another
+      float& f0 = x[(j + 4) % kStreams];
+      float& f1 = x[(j + 8) % kStreams];
+      float& f2 = x[(j + 12) % kStreams];
+      float& f3 = x[(j + 2) % kStreams];
+      float& f4 = x[(j + 6) % kStreams];
+      uint32_t& y0 = y[j];
+      uint32_t& y1 = y[(j + 4) % kStreams];
+      uint32_t& y2 = y[(j + 8) % kStreams];
+      uint32_t& y3 = y[(j + 12) % kStreams];
+      if (OP == 21) {
+        asm volatile("v_sin_f32 %0, %0" : "+v"(x[j]));
+        asm volatile("v_fma_f32 %0, %0, %4, %5\n v_fma_f32 %1, %1, %4, %5\n v_fma_f32 %2, %2, %4, %5\n v_fma_f32 %3, %3, %4, %5"
+                     : "+v"(f0), "+v"(f1), "+v"(f2), "+v"(f3) : "v"(a), "v"(b));
+      }
+      if (OP == 22) {
+        asm volatile("v_mul_lo_u32 %0, %0, %4\n v_mul_lo_u32 %1, %1, %4\n v_mul_lo_u32 %2, %2, %4\n v_mul_lo_u32 %3, %3, %4"
+                     : "+v"(y0), "+v"(y1), "+v"(y2), "+v"(y3) : "v"(ia));
+        asm volatile("v_fma_f32 %0, %0, %4, %5\n v_fma_f32 %1, %1, %4, %5\n v_fma_f32 %2, %2, %4, %5\n v_fma_f32 %3, %3, %4, %5"
+                     : "+v"(f0), "+v"(f1), "+v"(f2), "+v"(f3) : "v"(a), "v"(b));
+      }
+      if (OP == 23) {
+        asm volatile("v_sin_f32 %0, %0" : "+v"(x[j]));
+        asm volatile("v_mul_lo_u32 %0, %0, %4\n v_mul_lo_u32 %1, %1, %4\n v_mul_lo_u32 %2, %2, %4\n v_mul_lo_u32 %3, %3, %4"
+                     : "+v"(y0), "+v"(y1), "+v"(y2), "+v"(y3) : "v"(ia));
+        asm volatile("v_fma_f32 %0, %0, %4, %5\n v_fma_f32 %1, %1, %4, %5\n v_fma_f32 %2, %2, %4, %5\n v_fma_f32 %3, %3, %4, %5"
+                     : "+v"(f0), "+v"(f1), "+v"(f2), "+v"(f3) : "v"(a), "v"(b));
+      }
+      if (OP == 24 || OP == 25) {
+        // one (particle, wave vector) term: phase (3 mul_lo, add3, alignbit), sin, cos, then
+        // the force pass's 5 FP32 ops or the rho pass's 2
+        asm volatile("v_sin_f32 %0, %0" : "+v"(x[j]));
+        asm volatile("v_cos_f32 %0, %0" : "+v"(x[(j + 1) % kStreams]));
+        asm volatile("v_mul_lo_u32 %0, %0, %4\n v_mul_lo_u32 %1, %1, %4\n v_mul_lo_u32 %2, %2, %4\n v_add3_u32 %3, %3, %4, %5\n v_alignbit_b32 %0, %5, %0, 9"
+                     : "+v"(y0), "+v"(y1), "+v"(y2), "+v"(y3) : "v"(ia), "v"(ib));
+        if (OP == 24)
+          asm volatile("v_fma_f32 %0, %0, %5, %6\n v_fma_f32 %1, %1, %5, %6\n v_fma_f32 %2, %2, %5, %6\n v_fma_f32 %3, %3, %5, %6\n v_fma_f32 %4, %4, %5, %6"
+                       : "+v"(f0), "+v"(f1), "+v"(f2), "+v"(f3), "+v"(f4) : "v"(a), "v"(b));
+        else
+          asm volatile("v_fma_f32 %0, %0, %2, %3\n v_fma_f32 %1, %1, %2, %3" : "+v"(f0), "+v"(f1) : "v"(a), "v"(b));
+      }
       if (OP == 14) {
         asm volatile("v_sin_f32 %0, %0" : "+v"(x[j]));
         asm volatile("v_cos_f32 %0, %0" : "+v"(x[(j + 4) % kStreams]));
@@ -166,6 +210,11 @@ int main() {
   time_op<18>(blocks, lds, f, clk, n_out, h, &ms[18], &ghz[18]);
   time_op<19>(blocks, lds, f, clk, n_out, h, &ms[19], &ghz[19]);
   time_op<20>(blocks, lds, f, clk, n_out, h, &ms[20], &ghz[20]);
+  time_op<21>(blocks, lds, f, clk, n_out, h, &ms[21], &ghz[21]);
+  time_op<22>(blocks, lds, f, clk, n_out, h, &ms[22], &ghz[22]);
+  time_op<23>(blocks, lds, f, clk, n_out, h, &ms[23], &ghz[23]);
+  time_op<24>(blocks, lds, f, clk, n_out, h, &ms[24], &ghz[24]);
+  time_op<25>(blocks, lds, f, clk, n_out, h, &ms[25], &ghz[25]);
   std::printf("%d waves per SIMD, %d independent streams per lane, %d steps\n", wps, kStreams, kIter);
   std::printf("%-36s %8s %8s %14s %14s %12s\n", "instruction (per step)", "ms", "GHz", "ops/CU/clk@2.4", "ops/CU/clk@own",
               "cyc/wave64");
