@@ -205,7 +205,10 @@ rbe_status rbe_structure_factor(const rbe_plan *plan, const double *x, const dou
  * rho: (dev) the output of rbe_structure_factor for the same inputs.
  * F: (dev) 3*N_total values, FP64 for RBE_FP64, FP32 for RBE_FP32_MIXED and RBE_FP32.
  * U: (dev) B FP64 values.  In RBE_PHASE_CACHED mode the phase cache in ws
- * must come from rbe_structure_factor on the same positions.
+ * must come from rbe_structure_factor on the same positions.  In the FP32
+ * precisions the call first writes one 32-byte row per wave vector (m, c_l
+ * times rho) into ws with a small kernel; rbe_evaluate and the graph have the
+ * cross-tile reduction write these rows instead.
  */
 rbe_status rbe_kspace_force(const rbe_plan *plan, const double *x, const double *y,
                             const double *z, const double *q, const int32_t *m,

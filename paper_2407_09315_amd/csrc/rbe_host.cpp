@@ -119,7 +119,7 @@ struct rbe_plan {
   int64_t cdf_stride = kCdfHeader;   // doubles per system table
   // workspace layout (byte offsets)
   size_t off_sys = 0, off_rho = 0, off_force = 0, off_kred = 0, off_cdf = 0, off_part = 0,
-         off_xy = 0, off_cache = 0, total = 0;
+         off_xy = 0, off_cache = 0, off_frows = 0, total = 0;
   size_t ws_bytes = 0;      // workspace size: the largest layout over all variants
   int64_t n_partials = 0;   // complex slots
   int64_t n_cache = 0;      // (cos, sin) pairs
@@ -161,7 +161,7 @@ void build_layout(rbe_plan* p) {
     part += (int64_t)s.ntiles * s.p;
     s.cache_off = cache;
     if (p->cached) cache += (int64_t)s.n * s.p;
-    for (int32_t l = 0; l < s.p; ++l) p->kred[(size_t)(s.k_off + l)] = KRed{s.part_off + (int64_t)l * s.ntiles, s.ntiles, 0};
+    for (int32_t l = 0; l < s.p; ++l) p->kred[(size_t)(s.k_off + l)] = KRed{s.part_off + (int64_t)l * s.ntiles, s.ntiles, b};
     const int nf = std::max(1, (s.n + fchunk - 1) / fchunk);
     for (int f = 0; f < nf; ++f) {
       const int p0 = f * fchunk;
@@ -248,6 +248,7 @@ void build_layout(rbe_plan* p) {
   p->off_part = o;  o = align_up(o + 2 * sizeof(double) * (size_t)p->n_partials);
   p->off_xy = o;    o = align_up(o + 2 * sizeof(double) * (size_t)p->p_total());
   p->off_cache = o; o = align_up(o + 2 * sizeof(float) * (size_t)p->n_cache);
+  p->off_frows = o; o = align_up(o + sizeof(ForceRowF32) * (size_t)p->p_total());
   p->total = std::max<size_t>(o, kAlign);
 }
 
@@ -262,6 +263,7 @@ WsView view_of(const rbe_plan* p, void* ws) {
   w.partials = reinterpret_cast<double*>(b + p->off_part);
   w.xy = reinterpret_cast<double*>(b + p->off_xy);
   w.cache = reinterpret_cast<float*>(b + p->off_cache);
+  w.frows = reinterpret_cast<ForceRowF32*>(b + p->off_frows);
   return w;
 }
 
@@ -507,7 +509,8 @@ rbe_status rbe_structure_factor(const rbe_plan* p, const double* x, const double
   const int64_t n = p->n_total(), P = p->p_total();
   if (!need(x, n) || !need(y, n) || !need(z, n) || !need(q, n)) return fail(RBE_EINVAL, "NULL position/charge array");
   if (!need(m, P) || !need(rho, P)) return fail(RBE_EINVAL, "NULL m or rho array");
-  hipError_t e = launch_rho(shape_of(p), view_of(p, ws), x, y, z, q, m, rho, static_cast<hipStream_t>(stream));
+  hipError_t e = launch_rho(shape_of(p), view_of(p, ws), x, y, z, q, m, nullptr, rho, 0,
+                            static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "rho pass launch");
   return RBE_OK;
 }
@@ -522,7 +525,7 @@ rbe_status rbe_kspace_force(const rbe_plan* p, const double* x, const double* y,
     return fail(RBE_EINVAL, "NULL position/charge/force array");
   if (!need(m, P) || !need(w, P) || !need(rho, P)) return fail(RBE_EINVAL, "NULL m, w or rho array");
   if (U == nullptr) return fail(RBE_EINVAL, "U is NULL");
-  hipError_t e = launch_force(shape_of(p), view_of(p, ws), x, y, z, q, m, w, rho, F, U, nullptr,
+  hipError_t e = launch_force(shape_of(p), view_of(p, ws), x, y, z, q, m, w, rho, F, U, nullptr, 0,
                               static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "force pass launch");
   return RBE_OK;
@@ -673,8 +676,9 @@ hipError_t enqueue_evaluation(const rbe_plan* p, uint64_t seed, uint64_t stream_
   const LaunchShape shape = shape_of(p);
   const WsView view = view_of(p, ws);
   hipError_t e = launch_sample(shape, view, seed, stream_base, step_counter, m, w, st);
-  if (e == hipSuccess) e = launch_rho(shape, view, x, y, z, q, m, rho, st);
-  if (e == hipSuccess) e = launch_force(shape, view, x, y, z, q, m, w, rho, F, U, step_counter, st);
+  // the reduction writes the force rows, so the force pass needs no kernel of its own for them
+  if (e == hipSuccess) e = launch_rho(shape, view, x, y, z, q, m, w, rho, 1, st);
+  if (e == hipSuccess) e = launch_force(shape, view, x, y, z, q, m, w, rho, F, U, step_counter, 1, st);
   return e;
 }
 

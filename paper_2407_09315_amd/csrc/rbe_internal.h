@@ -25,12 +25,23 @@ struct SysDesc {
 static_assert(sizeof(SysDesc) == 64, "SysDesc layout");
 
 // Reduction descriptor of one wave vector: its tile partials are slots
-// slot .. slot + ntiles - 1 (complex) of the partial-sum region.
+// slot .. slot + ntiles - 1 (complex) of the partial-sum region; sys is its system.
 struct KRed {
   int64_t slot;
   int32_t ntiles;
-  int32_t pad;
+  int32_t sys;
 };
+
+// Force-pass row of one wave vector in the FP32 forms (32 bytes): m_l, its float copy, and
+// c_l times the structure factor rotated onto the form's phases.  Written once per
+// evaluation; every force block copies its system's rows into LDS.
+struct ForceRowF32 {
+  int32_t mx, my, mz;
+  float a;              // c_l * S'_l
+  float fx, fy, fz;     // m_l as float
+  float b;              // c_l * C'_l
+};
+static_assert(sizeof(ForceRowF32) == 32, "ForceRowF32 layout");
 
 // Sampler table of system b: cdf[b * stride ...] = S, 2M+1, p, k_off (as doubles), then the
 // 2M+1 prefix sums (zero-padded to the stride), so a table's address needs no other lookup.
@@ -81,6 +92,7 @@ struct WsView {
   double* partials;      // complex partial sums (rho pass, then VJP pass B1)
   double* xy;            // P_total complex values (VJP X + iY)
   float* cache;          // (cos, sin) phase cache, FP32_MIXED + CACHED only
+  ForceRowF32* frows;    // P_total force-pass rows (FP32 forms)
 };
 
 struct LaunchShape {
@@ -104,12 +116,16 @@ struct LaunchShape {
 };
 
 // Kernel launchers (rbe_kernels.hip).  Each returns hipSuccess or the launch error.
+// launch_rho with rows != 0 (FP32 forms) also writes the force rows from the reduced rho (wk:
+// the weights); launch_force with rows_ready != 0 uses them, otherwise it writes them from
+// rho first.
 hipError_t launch_rho(const LaunchShape& s, const WsView& w, const double* x, const double* y,
-                      const double* z, const double* q, const int32_t* m, double* rho,
-                      hipStream_t st);
+                      const double* z, const double* q, const int32_t* m, const double* wk, double* rho,
+                      int rows, hipStream_t st);
 hipError_t launch_force(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                         const double* z, const double* q, const int32_t* m, const double* wk,
-                        const double* rho, void* F, double* U, uint64_t* counter, hipStream_t st);
+                        const double* rho, void* F, double* U, uint64_t* counter, int rows_ready,
+                        hipStream_t st);
 hipError_t launch_vjp(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                       const double* z, const double* q, const int32_t* m, const double* wk,
                       const double* rho, const double* gU, const void* gF, void* gr, void* gq,

@@ -536,12 +536,37 @@ __global__ __launch_bounds__(64 * WPB) void rho_f64_kernel(WsView w, const doubl
 
 // ------------------------------------------------------------------ cross-tile reduction
 
+// Force-pass row of wave vector g of system sd from the reduced rho (C, S): c_l from the
+// weight and |k_l|^2, and c_l times rho rotated by exp(-i delta) back onto the truncated
+// phases of the FP32-mixed form (delta = 0 otherwise).
+__device__ inline ForceRowF32 force_row(const SysDesc& sd, int64_t g, const int32_t* __restrict__ m,
+                                        const double* __restrict__ wk, double C, double S, double rot_c,
+                                        double rot_s) {
+  const double invL = 1.0 / sd.L;
+  const double kscale = kTwoPi * invL;
+  const double vol = sd.L * sd.L * sd.L;
+  const int32_t mx = m[3 * g], my = m[3 * g + 1], mz = m[3 * g + 2];
+  const double k2 = kscale * kscale * ((double)mx * mx + (double)my * my + (double)mz * mz);
+  const double c = (k2 > 0.0) ? wk[g] * kFourPi / (vol * k2) : 0.0;
+  const double Cr = C * rot_c + S * rot_s;
+  const double Sr = S * rot_c - C * rot_s;
+  ForceRowF32 r;
+  r.mx = mx; r.my = my; r.mz = mz;
+  r.a = (float)(c * Sr);
+  r.b = (float)(c * Cr);
+  r.fx = (float)mx; r.fy = (float)my; r.fz = (float)mz;
+  return r;
+}
+
 // One block per wave vector: out[g] = sum over the system's tiles of partial[g][tile].
 // Thread t sums tiles t, t + 256, ... in order, each wave combines its lanes with a fixed
 // butterfly, and thread 0 adds the four wave sums in order; the result is optionally
-// rotated by exp(i delta).
+// rotated by exp(i delta).  With ROWS, thread 0 also writes the wave vector's force row.
+template <bool ROWS>
 __global__ __launch_bounds__(kReduceBlock) void reduce_kernel(WsView w, double* __restrict__ out,
-                                                              double rot_c, double rot_s) {
+                                                              double rot_c, double rot_s,
+                                                              const int32_t* __restrict__ m,
+                                                              const double* __restrict__ wk) {
   constexpr int kWaves = kReduceBlock / 64;
   __shared__ double wsum[2][kWaves];
   const int64_t g = blockIdx.x;
@@ -574,9 +599,23 @@ __global__ __launch_bounds__(kReduceBlock) void reduce_kernel(WsView w, double* 
       re += wsum[0][i];
       im += wsum[1][i];
     }
-    out[2 * g] = re * rot_c - im * rot_s;
-    out[2 * g + 1] = re * rot_s + im * rot_c;
+    const double C = re * rot_c - im * rot_s;
+    const double S = re * rot_s + im * rot_c;
+    out[2 * g] = C;
+    out[2 * g + 1] = S;
+    if (ROWS) w.frows[g] = force_row(w.sys[r.sys], g, m, wk, C, S, rot_c, rot_s);
   }
+}
+
+// Force rows of every wave vector from a given rho (a force pass without a reduction before it).
+__global__ __launch_bounds__(kReduceBlock) void force_rows_kernel(WsView w, int64_t p_total,
+                                                                  const int32_t* __restrict__ m,
+                                                                  const double* __restrict__ wk,
+                                                                  const double* __restrict__ rho,
+                                                                  double rot_c, double rot_s) {
+  const int64_t g = (int64_t)blockIdx.x * kReduceBlock + threadIdx.x;
+  if (g >= p_total) return;
+  w.frows[g] = force_row(w.sys[w.kred[g].sys], g, m, wk, rho[2 * g], rho[2 * g + 1], rot_c, rot_s);
 }
 
 // ------------------------------------------------------------------ virial
@@ -643,20 +682,16 @@ __device__ inline double block_sum(double v, double* red) {
 
 // ------------------------------------------------------------------ force pass, FP32-mixed
 
-struct TabF32 {
-  int32_t mx, my, mz;
-  float a;              // c_l * S'_l
-  float fx, fy, fz;     // m_l as float
-  float b;              // c_l * C'_l
-};
+using TabF32 = ForceRowF32;   // the force kernel's LDS table rows
 
 template <int NPLF, bool CACHED, bool FPH>
 __global__ __launch_bounds__(kForceBlock) void force_f32_kernel(
     WsView w, int64_t n_total, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const double* __restrict__ q, const int32_t* __restrict__ m,
-    const double* __restrict__ wk, const double* __restrict__ rho, float* __restrict__ F,
-    double* __restrict__ U, double rot_c, double rot_s, int32_t n_items, uint64_t* __restrict__ counter) {
-  __shared__ TabF32 tab[kTabChunk];
+    const double* __restrict__ wk, const double* __restrict__ rho, const ForceRowF32* __restrict__ frows,
+    float* __restrict__ F, double* __restrict__ U, int32_t n_items, uint64_t* __restrict__ counter) {
+  static_assert(kTabChunk == kForceBlock, "one table row per thread and chunk");
+  __shared__ __align__(16) TabF32 tab[kTabChunk];
   __shared__ double red[kForceBlock];
 for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
   const ForceItem it = w.force_items[item];
@@ -665,6 +700,13 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
   const double invL = 1.0 / sd.L;
   const double kscale = kTwoPi * invL;
   const double vol = sd.L * sd.L * sd.L;
+  // this thread's row of the first table chunk (two 16-byte halves), requested before the
+  // particles so that the two loads overlap.  The load is unconditional (a valid address for
+  // every thread: a clamped row, or the system table when the system has no rows), so the
+  // particle loads need not wait for it; only rows e < P are stored.
+  const int4* rows = reinterpret_cast<const int4*>(frows + sd.k_off);
+  const int4* r0 = sd.p > 0 ? rows + 2 * min(tid, sd.p - 1) : reinterpret_cast<const int4*>(w.sys);
+  const int4 row0a = r0[0], row0b = r0[1];
 
   using Ph = Phase<FPH>;
   typename Ph::Coord ux[NPLF], uy[NPLF], uz[NPLF];
@@ -684,25 +726,18 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
     }
     fx[j] = fy[j] = fz[j] = 0.0f;
   }
-  double usum = 0.0;
   for (int t0 = 0; t0 < sd.p; t0 += kTabChunk) {
     const int cnt = min(kTabChunk, sd.p - t0);
     __syncthreads();
-    for (int e = tid; e < cnt; e += kForceBlock) {
-      const int64_t g = sd.k_off + t0 + e;
-      const int32_t mx = m[3 * g], my = m[3 * g + 1], mz = m[3 * g + 2];
-      const double k2 = kscale * kscale * ((double)mx * mx + (double)my * my + (double)mz * mz);
-      const double c = (k2 > 0.0) ? wk[g] * kFourPi / (vol * k2) : 0.0;
-      const double C = rho[2 * g], S = rho[2 * g + 1];
-      const double Cr = C * rot_c + S * rot_s;
-      const double Sr = S * rot_c - C * rot_s;
-      TabF32 tb;
-      tb.mx = mx; tb.my = my; tb.mz = mz;
-      tb.a = (float)(c * Sr);
-      tb.b = (float)(c * Cr);
-      tb.fx = (float)mx; tb.fy = (float)my; tb.fz = (float)mz;
-      tab[e] = tb;
-      if (it.flags & 1) usum += 0.5 * c * (C * C + S * S);
+    if (tid < cnt) {
+      int4* dst = reinterpret_cast<int4*>(tab + tid);
+      if (t0 == 0) {
+        dst[0] = row0a;
+        dst[1] = row0b;
+      } else {
+        dst[0] = rows[2 * (t0 + tid)];
+        dst[1] = rows[2 * (t0 + tid) + 1];
+      }
     }
     // zero rows pad the chunk to a multiple of kUnroll (m = 0, a = b = 0: no contribution)
     const int cntp = (cnt + kUnroll - 1) / kUnroll * kUnroll;
@@ -757,6 +792,16 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
     }
   }
   if (it.flags & 1) {
+    // energy of the system in FP64: U = sum_l (c_l / 2) |rho_l|^2, thread t over l = t, t + 256, ...
+    double usum = 0.0;
+    for (int l = tid; l < sd.p; l += kForceBlock) {
+      const int64_t g = sd.k_off + l;
+      const int32_t mx = m[3 * g], my = m[3 * g + 1], mz = m[3 * g + 2];
+      const double k2 = kscale * kscale * ((double)mx * mx + (double)my * my + (double)mz * mz);
+      const double c = (k2 > 0.0) ? wk[g] * kFourPi / (vol * k2) : 0.0;
+      const double C = rho[2 * g], S = rho[2 * g + 1];
+      usum += 0.5 * c * (C * C + S * S);
+    }
     const double tot = block_sum(usum, red);
     if (tid == 0) {
       U[it.sys] = tot;
@@ -1260,9 +1305,9 @@ void truncation_rotation(int precision, double* c, double* s) {
 template <int NPLF, bool CACHED, bool FPH>
 void force_f32_t(const LaunchShape& s, const WsView& w, const double* x, const double* y, const double* z,
                  const double* q, const int32_t* m, const double* wk, const double* rho, float* F, double* U,
-                 double rc, double rs, uint64_t* counter, hipStream_t st) {
+                 uint64_t* counter, hipStream_t st) {
   hipLaunchKernelGGL((force_f32_kernel<NPLF, CACHED, FPH>), grid_for(s.n_force_items, s.force_grid_cap),
-                     dim3(kForceBlock), 0, st, w, s.n_total, x, y, z, q, m, wk, rho, F, U, rc, rs,
+                     dim3(kForceBlock), 0, st, w, s.n_total, x, y, z, q, m, wk, rho, w.frows, F, U,
                      s.n_force_items, counter);
 }
 
@@ -1277,8 +1322,8 @@ void force_f64_t(const LaunchShape& s, const WsView& w, const double* x, const d
 }  // namespace
 
 hipError_t launch_rho(const LaunchShape& s, const WsView& w, const double* x, const double* y,
-                      const double* z, const double* q, const int32_t* m, double* rho,
-                      hipStream_t st) {
+                      const double* z, const double* q, const int32_t* m, const double* wk, double* rho,
+                      int rows, hipStream_t st) {
   if (s.n_rho_items > 0) {
     if (s.ev_rho_begin != nullptr) (void)hipEventRecord(s.ev_rho_begin, st);
     launch_tile_pass<false>(s, w, x, y, z, q, m, nullptr, st);
@@ -1289,7 +1334,12 @@ hipError_t launch_rho(const LaunchShape& s, const WsView& w, const double* x, co
   if (s.p_total > 0) {
     double rc, rs;
     truncation_rotation(s.precision, &rc, &rs);
-    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)s.p_total), dim3(kReduceBlock), 0, st, w, rho, rc, rs);
+    if (rows != 0 && s.precision != RBE_FP64)
+      hipLaunchKernelGGL(reduce_kernel<true>, dim3((unsigned)s.p_total), dim3(kReduceBlock), 0, st, w, rho, rc, rs,
+                         m, wk);
+    else
+      hipLaunchKernelGGL(reduce_kernel<false>, dim3((unsigned)s.p_total), dim3(kReduceBlock), 0, st, w, rho, rc,
+                         rs, nullptr, nullptr);
     return hipGetLastError();
   }
   return hipSuccess;
@@ -1297,32 +1347,39 @@ hipError_t launch_rho(const LaunchShape& s, const WsView& w, const double* x, co
 
 hipError_t launch_force(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                         const double* z, const double* q, const int32_t* m, const double* wk,
-                        const double* rho, void* F, double* U, uint64_t* counter, hipStream_t st) {
+                        const double* rho, void* F, double* U, uint64_t* counter, int rows_ready,
+                        hipStream_t st) {
   if (s.n_force_items == 0) return hipSuccess;
-  if (s.ev_force_begin != nullptr) (void)hipEventRecord(s.ev_force_begin, st);
-  if (s.precision == RBE_FP32_MIXED) {
+  if (s.precision != RBE_FP64 && rows_ready == 0 && s.p_total > 0) {
     double rc, rs;
     truncation_rotation(s.precision, &rc, &rs);
+    hipLaunchKernelGGL(force_rows_kernel, dim3((unsigned)((s.p_total + kReduceBlock - 1) / kReduceBlock)),
+                       dim3(kReduceBlock), 0, st, w, s.p_total, m, wk, rho, rc, rs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (s.ev_force_begin != nullptr) (void)hipEventRecord(s.ev_force_begin, st);
+  if (s.precision == RBE_FP32_MIXED) {
     float* Ff = static_cast<float*>(F);
     if (s.cached) {
       switch (s.fv.nplf) {
-        case 1: force_f32_t<1, true, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
-        case 2: force_f32_t<2, true, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
-        default: force_f32_t<4, true, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
+        case 1: force_f32_t<1, true, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, counter, st); break;
+        case 2: force_f32_t<2, true, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, counter, st); break;
+        default: force_f32_t<4, true, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, counter, st); break;
       }
     } else {
       switch (s.fv.nplf) {
-        case 1: force_f32_t<1, false, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
-        case 2: force_f32_t<2, false, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
-        default: force_f32_t<4, false, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, rc, rs, counter, st); break;
+        case 1: force_f32_t<1, false, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, counter, st); break;
+        case 2: force_f32_t<2, false, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, counter, st); break;
+        default: force_f32_t<4, false, false>(s, w, x, y, z, q, m, wk, rho, Ff, U, counter, st); break;
       }
     }
   } else if (s.precision == RBE_FP32) {
     float* Ff = static_cast<float*>(F);
     switch (s.fv.nplf) {
-      case 1: force_f32_t<1, false, true>(s, w, x, y, z, q, m, wk, rho, Ff, U, 1.0, 0.0, counter, st); break;
-      case 2: force_f32_t<2, false, true>(s, w, x, y, z, q, m, wk, rho, Ff, U, 1.0, 0.0, counter, st); break;
-      default: force_f32_t<4, false, true>(s, w, x, y, z, q, m, wk, rho, Ff, U, 1.0, 0.0, counter, st); break;
+      case 1: force_f32_t<1, false, true>(s, w, x, y, z, q, m, wk, rho, Ff, U, counter, st); break;
+      case 2: force_f32_t<2, false, true>(s, w, x, y, z, q, m, wk, rho, Ff, U, counter, st); break;
+      default: force_f32_t<4, false, true>(s, w, x, y, z, q, m, wk, rho, Ff, U, counter, st); break;
     }
   } else {
     double* Fd = static_cast<double*>(F);
@@ -1349,7 +1406,8 @@ hipError_t launch_vjp(const LaunchShape& s, const WsView& w, const double* x, co
     if (e != hipSuccess) return e;
   }
   if (s.p_total > 0) {
-    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)s.p_total), dim3(kReduceBlock), 0, st, w, w.xy, rc, rs);
+    hipLaunchKernelGGL(reduce_kernel<false>, dim3((unsigned)s.p_total), dim3(kReduceBlock), 0, st, w, w.xy, rc, rs,
+                       nullptr, nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
