@@ -284,6 +284,7 @@ LaunchShape shape_of(const rbe_plan* p) {
   s.rho_grid_cap = p->rho_grid_cap;
   s.rho_clamp = p->rho_clamp;
   s.force_grid_cap = p->force_grid_cap;
+  s.sys0 = p->B == 1 ? p->sys[0] : SysDesc{};
   s.ev_rho_begin = p->ev[0];
   s.ev_rho_end = p->ev[1];
   s.ev_force_begin = p->ev[2];

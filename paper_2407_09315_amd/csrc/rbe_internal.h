@@ -111,6 +111,7 @@ struct LaunchShape {
   int32_t rho_grid_cap;  // persistent-grid caps (0: one block per work item)
   int32_t rho_clamp;     // 1: cap the rho-pass blocks per CU at their even share
   int32_t force_grid_cap;
+  SysDesc sys0;          // the system when B == 1 (then work items follow from the block index)
   // optional events recorded right before / after the rho-pass and force-pass kernels
   hipEvent_t ev_rho_begin, ev_rho_end, ev_force_begin, ev_force_end;
 };

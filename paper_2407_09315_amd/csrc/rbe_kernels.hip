@@ -689,13 +689,25 @@ __global__ __launch_bounds__(kForceBlock) void force_f32_kernel(
     WsView w, int64_t n_total, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const double* __restrict__ q, const int32_t* __restrict__ m,
     const double* __restrict__ wk, const double* __restrict__ rho, const ForceRowF32* __restrict__ frows,
-    float* __restrict__ F, double* __restrict__ U, int32_t n_items, uint64_t* __restrict__ counter) {
+    float* __restrict__ F, double* __restrict__ U, int32_t n_items, uint64_t* __restrict__ counter, SysDesc sys0,
+    int32_t single) {
   static_assert(kTabChunk == kForceBlock, "one table row per thread and chunk");
   __shared__ __align__(16) TabF32 tab[kTabChunk];
   __shared__ double red[kForceBlock];
 for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-  const ForceItem it = w.force_items[item];
-  const SysDesc sd = w.sys[it.sys];
+  // with one system the item and the system follow from the block index and the arguments
+  // (the items are consecutive particle ranges of 256 NPLF), so no load precedes the
+  // particle and row loads
+  ForceItem it;
+  SysDesc sd;
+  if (single) {
+    const int p0 = item * (kForceBlock * NPLF);
+    it = ForceItem{0, p0, max(0, min(kForceBlock * NPLF, sys0.n - p0)), item == 0 ? 1 : 0};
+    sd = sys0;
+  } else {
+    it = w.force_items[item];
+    sd = w.sys[it.sys];
+  }
   const int tid = threadIdx.x;
   const double invL = 1.0 / sd.L;
   const double kscale = kTwoPi * invL;
@@ -1308,7 +1320,7 @@ void force_f32_t(const LaunchShape& s, const WsView& w, const double* x, const d
                  uint64_t* counter, hipStream_t st) {
   hipLaunchKernelGGL((force_f32_kernel<NPLF, CACHED, FPH>), grid_for(s.n_force_items, s.force_grid_cap),
                      dim3(kForceBlock), 0, st, w, s.n_total, x, y, z, q, m, wk, rho, w.frows, F, U,
-                     s.n_force_items, counter);
+                     s.n_force_items, counter, s.sys0, s.B == 1 ? 1 : 0);
 }
 
 template <int NPLF>
