@@ -724,29 +724,44 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
   typename Ph::Coord ux[NPLF], uy[NPLF], uz[NPLF];
   float fx[NPLF], fy[NPLF], fz[NPLF];
   int li[NPLF];
+  double cx[NPLF], cy[NPLF], cz[NPLF];   // the particles as loaded
 #pragma unroll
   for (int j = 0; j < NPLF; ++j) {
     li[j] = it.p0 + j * kForceBlock + tid;
     const bool ok = j * kForceBlock + tid < it.np;
+    cx[j] = cy[j] = cz[j] = 0.0;
     if (ok && !CACHED) {
       const int64_t gi = sd.n_off + li[j];
-      ux[j] = Ph::coord(x[gi], invL);
-      uy[j] = Ph::coord(y[gi], invL);
-      uz[j] = Ph::coord(z[gi], invL);
-    } else {
-      ux[j] = uy[j] = uz[j] = 0;
+      cx[j] = x[gi];
+      cy[j] = y[gi];
+      cz[j] = z[gi];
     }
     fx[j] = fy[j] = fz[j] = 0.0f;
   }
+  // the first chunk's rows go to LDS as soon as they arrive (once the previous item's
+  // readers are done), which frees their registers before the particles are converted
+  __syncthreads();
+  if (tid < min(kTabChunk, sd.p)) {
+    int4* dst = reinterpret_cast<int4*>(tab + tid);
+    dst[0] = row0a;
+    dst[1] = row0b;
+  }
+#pragma unroll
+  for (int j = 0; j < NPLF; ++j) {
+    if (j * kForceBlock + tid < it.np && !CACHED) {
+      ux[j] = Ph::coord(cx[j], invL);
+      uy[j] = Ph::coord(cy[j], invL);
+      uz[j] = Ph::coord(cz[j], invL);
+    } else {
+      ux[j] = uy[j] = uz[j] = 0;
+    }
+  }
   for (int t0 = 0; t0 < sd.p; t0 += kTabChunk) {
     const int cnt = min(kTabChunk, sd.p - t0);
-    __syncthreads();
-    if (tid < cnt) {
-      int4* dst = reinterpret_cast<int4*>(tab + tid);
-      if (t0 == 0) {
-        dst[0] = row0a;
-        dst[1] = row0b;
-      } else {
+    if (t0 > 0) {
+      __syncthreads();
+      if (tid < cnt) {
+        int4* dst = reinterpret_cast<int4*>(tab + tid);
         dst[0] = rows[2 * (t0 + tid)];
         dst[1] = rows[2 * (t0 + tid) + 1];
       }
