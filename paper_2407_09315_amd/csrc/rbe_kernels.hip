@@ -117,6 +117,32 @@ __device__ inline void sincos_turns(double r, double* s, double* c) {
   *c = fma(pc, cq, -(sn * sq));
 }
 
+// Table of (cos, sin) of 2 pi q / kTurnSteps for q = -kTurnSteps/2 .. kTurnSteps/2 (4 KB of
+// LDS), built by a block from sincos_turns.
+constexpr int kTurnRows = kTurnSteps + 1;
+__device__ inline void build_turn_table(double2* tab) {
+  for (int i = threadIdx.x; i < kTurnRows; i += blockDim.x) {
+    double s, c;
+    sincos_turns((double)(i - kTurnSteps / 2) * (1.0 / kTurnSteps), &s, &c);
+    tab[i] = make_double2(c, s);
+  }
+}
+
+// sin and cos of 2 pi r for |r| <= 1/2 (turns), FP64, from the table: with q = rint(r N)
+// (N = kTurnSteps) and f = r - q/N (exact, |f| <= 1/(2N)), exp(2 pi i r) = t_q exp(2 pi i f),
+// where the short polynomials give sin(2 pi f) and cos(2 pi f) - 1, which are small, so
+// the products with the table entry are corrections added to it.
+__device__ inline void sincos_turns_tab(double r, const double2* tab, double* s, double* c) {
+  const double q = rint(r * (double)kTurnSteps);
+  const double f = fma(q, -1.0 / kTurnSteps, r);
+  const double u = f * f;
+  const double sf = f * fma(fma(kSinShort[2], u, kSinShort[1]), u, kSinShort[0]);
+  const double cm1 = u * fma(fma(kCosm1Short[2], u, kCosm1Short[1]), u, kCosm1Short[0]);
+  const double2 t = tab[(int)q + kTurnSteps / 2];
+  *s = fma(t.y, cm1, fma(t.x, sf, t.y));
+  *c = fma(t.x, cm1, fma(-t.y, sf, t.x));
+}
+
 // phase of m.s in turns, reduced to [-1/2, 1/2].
 __device__ inline double phase_f64(double mx, double my, double mz, double sx, double sy, double sz) {
   const double t = fma(mx, sx, fma(my, sy, mz * sz));
@@ -449,6 +475,9 @@ __global__ __launch_bounds__(64 * WPB) void rho_f64_kernel(WsView w, const doubl
                                                           const double* __restrict__ gF, int64_t n_total,
                                                           int32_t n_items) {
   __shared__ int32_t sched_lds[WPB == kCoopWaves ? 2 * kCoopWaves : 1];
+  __shared__ double2 turns[kTurnRows];
+  build_turn_table(turns);
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int32_t wave = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
   RhoSchedule<WPB> sched(n_items, wave, sched_lds);
@@ -513,7 +542,7 @@ __global__ __launch_bounds__(64 * WPB) void rho_f64_kernel(WsView w, const doubl
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
           double sn, cs;
-          sincos_turns(phase_f64(mx[c], my[c], mz[c], sx[j], sy[j], sz[j]), &sn, &cs);
+          sincos_turns_tab(phase_f64(mx[c], my[c], mz[c], sx[j], sy[j], sz[j]), turns, &sn, &cs);
           double wt = qv[j];
           if (VJP) wt = fma(qgx[j], mx[c], fma(qgy[j], my[c], qgz[j] * mz[c]));
           acc[c] = fma(wt, cs, acc[c]);
@@ -855,6 +884,8 @@ __global__ __launch_bounds__(kForceBlock) void force_f64_kernel(
     double* __restrict__ U, int32_t n_items, uint64_t* __restrict__ counter) {
   __shared__ TabF64 tab[kTabChunk];
   __shared__ double red[kForceBlock];
+  __shared__ double2 turns[kTurnRows];
+  build_turn_table(turns);   // the item loop's first barrier precedes every use
 for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
   const ForceItem it = w.force_items[item];
   const SysDesc sd = w.sys[it.sys];
@@ -901,7 +932,7 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
 #pragma unroll
       for (int j = 0; j < NPLF; ++j) {
         double sn, cs;
-        sincos_turns(phase_f64(tb.mx, tb.my, tb.mz, sx[j], sy[j], sz[j]), &sn, &cs);
+        sincos_turns_tab(phase_f64(tb.mx, tb.my, tb.mz, sx[j], sy[j], sz[j]), turns, &sn, &cs);
         const double g = tb.a * cs - tb.b * sn;
         fx[j] = fma(g, tb.mx, fx[j]);
         fy[j] = fma(g, tb.my, fy[j]);
@@ -1061,6 +1092,8 @@ __global__ __launch_bounds__(kForceBlock) void vjp_b2_f64_kernel(
     const double* __restrict__ gF, double* __restrict__ gr, double* __restrict__ gq, int32_t n_items) {
   __shared__ double tabm[kTabChunk][3];
   __shared__ AdjTab tab[kTabChunk];
+  __shared__ double2 turns[kTurnRows];
+  build_turn_table(turns);   // the item loop's first barrier precedes every use
 for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
   const ForceItem it = w.force_items[item];
   const SysDesc sd = w.sys[it.sys];
@@ -1106,7 +1139,7 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
 #pragma unroll
       for (int j = 0; j < NPLF; ++j) {
         double sn, cs;
-        sincos_turns(phase_f64(mx, my, mz, sx[j], sy[j], sz[j]), &sn, &cs);
+        sincos_turns_tab(phase_f64(mx, my, mz, sx[j], sy[j], sz[j]), turns, &sn, &cs);
         const double gm = fma(gx[j], mx, fma(gy[j], my, gz[j] * mz));
         const double p1 = tb.z1i * cs - tb.z1r * sn;
         const double p2 = tb.z2r * cs + tb.z2i * sn;
@@ -1213,7 +1246,7 @@ dim3 grid_for(int32_t n_items, int32_t cap) {
 // would pack those CUs up to their register-limited occupancy and leave the rest short.
 // Reserving unused LDS per block caps the 4-wave blocks per CU at
 // ceil(items / (4 x CUs)), so every CU gets its share wherever the blocks land.
-size_t occupancy_clamp_lds(int32_t n_waves) {
+size_t occupancy_clamp_lds(int32_t n_waves, size_t static_bytes) {
   static int cus = 0, lds_per_cu = 0;
   if (cus == 0) {
     int dev = 0;
@@ -1226,8 +1259,8 @@ size_t occupancy_clamp_lds(int32_t n_waves) {
   }
   if (cus <= 0) return 0;
   const int64_t per_simd = std::max<int64_t>((n_waves + 4LL * cus - 1) / (4LL * cus), 1);
-  // 256 bytes below the share, which leaves room for the kernel's own static LDS
-  const int64_t bytes = (int64_t)(lds_per_cu / per_simd) / 256 * 256 - 256;
+  // the share less the kernel's own static LDS, with 256 bytes to spare
+  const int64_t bytes = (int64_t)(lds_per_cu / per_simd) / 256 * 256 - 256 - (int64_t)static_bytes;
   return (size_t)std::min<int64_t>(std::max<int64_t>(bytes, 0), 64 * 1024);
 }
 
@@ -1260,7 +1293,7 @@ void launch_rho_f32_t(const LaunchShape& s, const WsView& w, const double* x, co
                       const double* z, const double* q, const int32_t* m, const float* gF,
                       hipStream_t st) {
   const dim3 grid = rho_grid(s.n_rho_items, s.rho_grid_cap, WPB);
-  const size_t lds = (WPB == 4 && s.rho_clamp) ? occupancy_clamp_lds((int32_t)grid.x * 4) : 0;
+  const size_t lds = (WPB == 4 && s.rho_clamp) ? occupancy_clamp_lds((int32_t)grid.x * 4, 0) : 0;
   hipLaunchKernelGGL((rho_f32_kernel<NPL, KC, CACHE, VJP, FPH, WPB>), grid, dim3(64 * WPB), lds, st, w, x, y, z,
                      q, m, gF, s.n_total, s.n_rho_items);
 }
@@ -1270,7 +1303,7 @@ void launch_rho_f64_t(const LaunchShape& s, const WsView& w, const double* x, co
                       const double* z, const double* q, const int32_t* m, const double* gF,
                       hipStream_t st) {
   const dim3 grid = rho_grid(s.n_rho_items, s.rho_grid_cap, WPB);
-  const size_t lds = (WPB == 4 && s.rho_clamp) ? occupancy_clamp_lds((int32_t)grid.x * 4) : 0;
+  const size_t lds = (WPB == 4 && s.rho_clamp) ? occupancy_clamp_lds((int32_t)grid.x * 4, sizeof(double2) * kTurnRows) : 0;
   hipLaunchKernelGGL((rho_f64_kernel<NPL, KC, VJP, WPB>), grid, dim3(64 * WPB), lds, st, w, x, y, z, q, m, gF,
                      s.n_total, s.n_rho_items);
 }
