@@ -117,37 +117,41 @@ __device__ inline void sincos_turns(double r, double* s, double* c) {
   *c = fma(pc, cq, -(sn * sq));
 }
 
-// Table of (cos, sin) of 2 pi q / kTurnSteps for q = -kTurnSteps/2 .. kTurnSteps/2 (4 KB of
-// LDS), built by a block from sincos_turns.
-constexpr int kTurnRows = kTurnSteps + 1;
+// Table of (cos, sin) of 2 pi q / kTurnSteps for q = 0 .. kTurnSteps - 1 (4 KB of LDS),
+// built by a block from sincos_turns (rows past the half turn use q - kTurnSteps).
+constexpr int kTurnRows = kTurnSteps;
+static_assert((kTurnSteps & (kTurnSteps - 1)) == 0, "the table index is q mod kTurnSteps");
 __device__ inline void build_turn_table(double2* tab) {
   for (int i = threadIdx.x; i < kTurnRows; i += blockDim.x) {
     double s, c;
-    sincos_turns((double)(i - kTurnSteps / 2) * (1.0 / kTurnSteps), &s, &c);
+    const int qi = i <= kTurnSteps / 2 ? i : i - kTurnSteps;
+    sincos_turns((double)qi * (1.0 / kTurnSteps), &s, &c);
     tab[i] = make_double2(c, s);
   }
 }
 
-// sin and cos of 2 pi r for |r| <= 1/2 (turns), FP64, from the table: with q = rint(r N)
-// (N = kTurnSteps) and f = r - q/N (exact, |f| <= 1/(2N)), exp(2 pi i r) = t_q exp(2 pi i f),
-// where the short polynomials give sin(2 pi f) and cos(2 pi f) - 1, which are small, so
-// the products with the table entry are corrections added to it.
-__device__ inline void sincos_turns_tab(double r, const double2* tab, double* s, double* c) {
-  const double q = rint(r * (double)kTurnSteps);
-  const double f = fma(q, -1.0 / kTurnSteps, r);
+// sin and cos of 2 pi t for a phase t in turns (any size that keeps 256 t an exact
+// integer-valued double and q below 2^31), FP64, from the table: with q = rint(t N)
+// (N = kTurnSteps) and f = t - q/N (exact: q/N is exact and within a factor 2 of t
+// unless q = 0; |f| <= 1/(2N)), exp(2 pi i t) = t_(q mod N) exp(2 pi i f).  The short
+// polynomials give sin(2 pi f) and cos(2 pi f) - 1, which are small, so their products
+// with the table entry are corrections added to it.
+__device__ inline void sincos_phase_tab(double t, const double2* tab, double* s, double* c) {
+  const double q = rint(t * (double)kTurnSteps);
+  const double f = fma(q, -1.0 / kTurnSteps, t);
   const double u = f * f;
   const double sf = f * fma(fma(kSinShort[2], u, kSinShort[1]), u, kSinShort[0]);
   const double cm1 = u * fma(fma(kCosm1Short[2], u, kCosm1Short[1]), u, kCosm1Short[0]);
-  const double2 t = tab[(int)q + kTurnSteps / 2];
-  *s = fma(t.y, cm1, fma(t.x, sf, t.y));
-  *c = fma(t.x, cm1, fma(-t.y, sf, t.x));
+  const double2 e = tab[(int)q & (kTurnSteps - 1)];
+  *s = fma(e.y, cm1, fma(e.x, sf, e.y));
+  *c = fma(e.x, cm1, fma(-e.y, sf, e.x));
 }
 
-// phase of m.s in turns, reduced to [-1/2, 1/2].
-__device__ inline double phase_f64(double mx, double my, double mz, double sx, double sy, double sz) {
-  const double t = fma(mx, sx, fma(my, sy, mz * sz));
-  return t - rint(t);
+// phase m.s in turns (not reduced).
+__device__ inline double dot_f64(double mx, double my, double mz, double sx, double sy, double sz) {
+  return fma(mx, sx, fma(my, sy, mz * sz));
 }
+
 
 // ------------------------------------------------------------------ wave reductions
 
@@ -542,7 +546,7 @@ __global__ __launch_bounds__(64 * WPB) void rho_f64_kernel(WsView w, const doubl
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
           double sn, cs;
-          sincos_turns_tab(phase_f64(mx[c], my[c], mz[c], sx[j], sy[j], sz[j]), turns, &sn, &cs);
+          sincos_phase_tab(dot_f64(mx[c], my[c], mz[c], sx[j], sy[j], sz[j]), turns, &sn, &cs);
           double wt = qv[j];
           if (VJP) wt = fma(qgx[j], mx[c], fma(qgy[j], my[c], qgz[j] * mz[c]));
           acc[c] = fma(wt, cs, acc[c]);
@@ -932,7 +936,7 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
 #pragma unroll
       for (int j = 0; j < NPLF; ++j) {
         double sn, cs;
-        sincos_turns_tab(phase_f64(tb.mx, tb.my, tb.mz, sx[j], sy[j], sz[j]), turns, &sn, &cs);
+        sincos_phase_tab(dot_f64(tb.mx, tb.my, tb.mz, sx[j], sy[j], sz[j]), turns, &sn, &cs);
         const double g = tb.a * cs - tb.b * sn;
         fx[j] = fma(g, tb.mx, fx[j]);
         fy[j] = fma(g, tb.my, fy[j]);
@@ -1139,7 +1143,7 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
 #pragma unroll
       for (int j = 0; j < NPLF; ++j) {
         double sn, cs;
-        sincos_turns_tab(phase_f64(mx, my, mz, sx[j], sy[j], sz[j]), turns, &sn, &cs);
+        sincos_phase_tab(dot_f64(mx, my, mz, sx[j], sy[j], sz[j]), turns, &sn, &cs);
         const double gm = fma(gx[j], mx, fma(gy[j], my, gz[j] * mz));
         const double p1 = tb.z1i * cs - tb.z1r * sn;
         const double p2 = tb.z2r * cs + tb.z2i * sn;
