@@ -117,7 +117,7 @@ __device__ inline void sincos_turns(double r, double* s, double* c) {
   *c = fma(pc, cq, -(sn * sq));
 }
 
-// Table of (cos, sin) of 2 pi q / kTurnSteps for q = 0 .. kTurnSteps - 1 (4 KB of LDS),
+// Table of (cos, sin) of 2 pi q / kTurnSteps for q = 0 .. kTurnSteps - 1 (8 KB of LDS),
 // built by a block from sincos_turns (rows past the half turn use q - kTurnSteps).
 constexpr int kTurnRows = kTurnSteps;
 static_assert((kTurnSteps & (kTurnSteps - 1)) == 0, "the table index is q mod kTurnSteps");
@@ -130,24 +130,32 @@ __device__ inline void build_turn_table(double2* tab) {
   }
 }
 
-// sin and cos of 2 pi t for a phase t in turns (any size that keeps 256 t an exact
-// integer-valued double and q below 2^31), FP64, from the table: with q = rint(t N)
-// (N = kTurnSteps) and f = t - q/N (exact: q/N is exact and within a factor 2 of t
-// unless q = 0; |f| <= 1/(2N)), exp(2 pi i t) = t_(q mod N) exp(2 pi i f).  The short
-// polynomials give sin(2 pi f) and cos(2 pi f) - 1, which are small, so their products
-// with the table entry are corrections added to it.
+// Fractional coordinate frac(x / L) in units of 1/kTurnSteps turn (the product with the
+// power of two is exact), so that m.s comes out in the table's unit.
+__device__ inline double table_coord(double x, double invL) {
+  const double v = x * invL;
+  return (v - floor(v)) * (double)kTurnSteps;
+}
+
+// sin and cos of 2 pi t / N (N = kTurnSteps) for a phase t in units of 1/N turn (any size
+// that keeps q below 2^31), FP64, from the table: with q = rint(t) and g = t - q (exact:
+// q is within a factor 2 of t unless q = 0; |g| <= 1/2), exp(2 pi i t / N) =
+// t_(q mod N) exp(2 pi i g / N).  The short polynomials give sin(2 pi g / N) and
+// cos(2 pi g / N) - 1, which are small, so their products with the table entry are
+// corrections added to it.
 __device__ inline void sincos_phase_tab(double t, const double2* tab, double* s, double* c) {
-  const double q = rint(t * (double)kTurnSteps);
-  const double f = fma(q, -1.0 / kTurnSteps, t);
-  const double u = f * f;
-  const double sf = f * fma(fma(kSinShort[2], u, kSinShort[1]), u, kSinShort[0]);
-  const double cm1 = u * fma(fma(kCosm1Short[2], u, kCosm1Short[1]), u, kCosm1Short[0]);
+  const double q = rint(t);
+  const double g = t - q;
+  const double u = g * g;
+  static_assert(kSinShortTerms == 3 && kCosm1ShortTerms == 2, "the polynomials below are unrolled");
+  const double sf = g * fma(fma(kSinShort[2], u, kSinShort[1]), u, kSinShort[0]);
+  const double cm1 = u * fma(kCosm1Short[1], u, kCosm1Short[0]);
   const double2 e = tab[(int)q & (kTurnSteps - 1)];
   *s = fma(e.y, cm1, fma(e.x, sf, e.y));
   *c = fma(e.x, cm1, fma(-e.y, sf, e.x));
 }
 
-// phase m.s in turns (not reduced).
+// phase m.s (not reduced), in the unit of s.
 __device__ inline double dot_f64(double mx, double my, double mz, double sx, double sy, double sz) {
   return fma(mx, sx, fma(my, sy, mz * sz));
 }
@@ -506,10 +514,9 @@ __global__ __launch_bounds__(64 * WPB) void rho_f64_kernel(WsView w, const doubl
         const int li = j * 64 + lane;
         if (li < cnt) {
           const int64_t gi = sd.n_off + first + li;
-          const double vx = x[gi] * invL, vy = y[gi] * invL, vz = z[gi] * invL;
-          sx[j] = vx - floor(vx);
-          sy[j] = vy - floor(vy);
-          sz[j] = vz - floor(vz);
+          sx[j] = table_coord(x[gi], invL);
+          sy[j] = table_coord(y[gi], invL);
+          sz[j] = table_coord(z[gi], invL);
           qv[j] = q[gi];
           if (VJP) {
             qgx[j] = qv[j] * gF[gi];
@@ -904,10 +911,9 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
     const bool ok = j * kForceBlock + tid < it.np;
     if (ok) {
       const int64_t gi = sd.n_off + it.p0 + j * kForceBlock + tid;
-      const double vx = x[gi] * invL, vy = y[gi] * invL, vz = z[gi] * invL;
-      sx[j] = vx - floor(vx);
-      sy[j] = vy - floor(vy);
-      sz[j] = vz - floor(vz);
+      sx[j] = table_coord(x[gi], invL);
+      sy[j] = table_coord(y[gi], invL);
+      sz[j] = table_coord(z[gi], invL);
     } else {
       sx[j] = sy[j] = sz[j] = 0.0;
     }
@@ -1114,10 +1120,9 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
     const bool ok = j * kForceBlock + tid < it.np;
     if (ok) {
       const int64_t gi = sd.n_off + it.p0 + j * kForceBlock + tid;
-      const double vx = x[gi] * invL, vy = y[gi] * invL, vz = z[gi] * invL;
-      sx[j] = vx - floor(vx);
-      sy[j] = vy - floor(vy);
-      sz[j] = vz - floor(vz);
+      sx[j] = table_coord(x[gi], invL);
+      sy[j] = table_coord(y[gi], invL);
+      sz[j] = table_coord(z[gi], invL);
       gx[j] = gF[gi];
       gy[j] = gF[n_total + gi];
       gz[j] = gF[2 * n_total + gi];

@@ -1,6 +1,6 @@
 """Autotune the benchmark workloads and write the tuning cache.
 
-Usage: python -m paper_2407_09315_amd.tune_workloads [--out PATH]
+Usage: python -m paper_2407_09315_amd.tune_workloads [--out PATH] [--precisions fp64,...]
 Shapes: 3,000 charges (P=100), 300k water, 1M electrolyte (P=100, 200),
 10M electrolyte (P=100), 200k charges (P=100), 128 uneven replicas; each in
 FP64, FP32-mixed and FP32 (where the plan accepts FP32 phases).
@@ -48,12 +48,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=cache_path())
     ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--precisions", default="fp32,fp32_mixed,fp64",
+                    help="comma-separated precisions to tune; the cache keeps the other entries")
     args = ap.parse_args()
     dev = torch.device("cuda:0")
     for name, batch, systems in workloads():
         X = [torch.tensor(np.concatenate([getattr(s, a) for s in systems]), dtype=torch.float64, device=dev)
              for a in ("x", "y", "z", "q")]
-        for prec in ("fp32", "fp32_mixed", "fp64"):
+        for prec in args.precisions.split(","):
             try:
                 plan = Plan(batch, precision=prec, phase_mode="auto", tiles=None)
             except RBEError as e:   # FP32 phases are refused for large boxes
