@@ -63,14 +63,32 @@ __device__ inline float turns_arg(uint32_t t) {
   return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, t, 9u));
 }
 
-__device__ inline uint32_t phase_u32(int32_t mx, int32_t my, int32_t mz, uint32_t ux, uint32_t uy, uint32_t uz) {
-  return (uint32_t)mx * ux + (uint32_t)my * uy + (uint32_t)mz * uz;
+// m.u mod 2^32 from three v_mad_u64_u32 (32 x 32 + 64 -> 64 bits, issued at the rate of
+// v_mul_lo_u32): one half-rate instruction per term fewer than three v_mul_lo_u32 and a
+// v_add3_u32.  The low word of m u + c depends only on the low words of the operands, so
+// it is the phase mod 2^32 with m taken as unsigned.  The 64-bit sums go through an empty
+// asm (keep_u64) before their low words are used; otherwise the compiler narrows them back
+// to 32-bit multiplies and an add.  One asm covers a group of sums, so the group's
+// multiply-add chains can interleave.
+__device__ inline uint64_t phase_u64(int32_t mx, int32_t my, int32_t mz, uint32_t ux, uint32_t uy, uint32_t uz) {
+  uint64_t t = (uint64_t)(uint32_t)mz * uz;
+  t = (uint64_t)(uint32_t)my * uy + t;
+  return (uint64_t)(uint32_t)mx * ux + t;
+}
+template <int K> __device__ inline void keep_u64(uint64_t (&t)[K]);
+template <> __device__ inline void keep_u64<1>(uint64_t (&t)[1]) { asm("" : "+v"(t[0])); }
+template <> __device__ inline void keep_u64<2>(uint64_t (&t)[2]) { asm("" : "+v"(t[0]), "+v"(t[1])); }
+template <> __device__ inline void keep_u64<4>(uint64_t (&t)[4]) {
+  asm("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]));
+}
+template <> __device__ inline void keep_u64<8>(uint64_t (&t)[8]) {
+  asm("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]), "+v"(t[5]), "+v"(t[6]), "+v"(t[7]));
 }
 
 // Phase arithmetic of the FP32 passes.  Both give the argument of v_sin_f32 / v_cos_f32,
 // which take revolutions.
 //   Phase<false> (RBE_FP32_MIXED): 32-bit fixed-point fractions; m.s mod 1 is exact,
-//     then truncated to 23 bits (3 integer multiplies, add3, alignbit per term).
+//     then truncated to 23 bits (3 integer multiply-adds and alignbit per term).
 //   Phase<true> (RBE_FP32): fractions centred in [-1/2, 1/2] held in FP32 and the phase
 //     m.s by an FMA chain (3 ops per term).  Its rounding error grows with |m.s|, and
 //     v_sin / v_cos accept |m.s| <= 256 turns.
@@ -78,9 +96,23 @@ template <bool FPH> struct Phase;
 template <> struct Phase<false> {
   using Coord = uint32_t;
   __device__ static inline Coord coord(double x, double invL) { return fixed_fraction(x, invL); }
-  __device__ static inline float arg(int32_t mx, int32_t my, int32_t mz, float, float, float, Coord ux,
+  // K terms of one particle: a[c] for wave vector c
+  template <int K>
+  __device__ static inline void args(const int32_t (&mx)[K], const int32_t (&my)[K], const int32_t (&mz)[K],
+                                     const float (&)[K], const float (&)[K], const float (&)[K], Coord ux,
+                                     Coord uy, Coord uz, float (&a)[K]) {
+    uint64_t t[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) t[c] = phase_u64(mx[c], my[c], mz[c], ux, uy, uz);
+    keep_u64<K>(t);
+#pragma unroll
+    for (int c = 0; c < K; ++c) a[c] = turns_arg((uint32_t)t[c]);
+  }
+  __device__ static inline float arg(int32_t mx, int32_t my, int32_t mz, float fx, float fy, float fz, Coord ux,
                                      Coord uy, Coord uz) {
-    return turns_arg(phase_u32(mx, my, mz, ux, uy, uz));
+    float a[1];
+    args<1>({mx}, {my}, {mz}, {fx}, {fy}, {fz}, ux, uy, uz, a);
+    return a[0];
   }
 };
 template <> struct Phase<true> {
@@ -92,6 +124,13 @@ template <> struct Phase<true> {
   __device__ static inline float arg(int32_t, int32_t, int32_t, float fx, float fy, float fz, Coord ux,
                                      Coord uy, Coord uz) {
     return fmaf(fx, ux, fmaf(fy, uy, fz * uz));
+  }
+  template <int K>
+  __device__ static inline void args(const int32_t (&)[K], const int32_t (&)[K], const int32_t (&)[K],
+                                     const float (&fx)[K], const float (&fy)[K], const float (&fz)[K], Coord ux,
+                                     Coord uy, Coord uz, float (&a)[K]) {
+#pragma unroll
+    for (int c = 0; c < K; ++c) a[c] = fmaf(fx[c], ux, fmaf(fy[c], uy, fz[c] * uz));
   }
 };
 
@@ -431,9 +470,7 @@ __global__ __launch_bounds__(64 * WPB) void rho_f32_kernel(WsView w, const doubl
         float a[PAIRS][KC], sn[PAIRS][KC], cs[PAIRS][KC];
 #pragma unroll
         for (int jj = 0; jj < PAIRS; ++jj)
-#pragma unroll
-          for (int c = 0; c < KC; ++c)
-            a[jj][c] = Ph::arg(mx[c], my[c], mz[c], fmx[c], fmy[c], fmz[c], ux[j0 + jj], uy[j0 + jj], uz[j0 + jj]);
+          Ph::template args<KC>(mx, my, mz, fmx, fmy, fmz, ux[j0 + jj], uy[j0 + jj], uz[j0 + jj], a[jj]);
 #pragma unroll
         for (int jj = 0; jj < PAIRS; ++jj)
 #pragma unroll
@@ -830,9 +867,14 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
           }
         } else {
           float a[kUnroll];
+          int32_t rmx[kUnroll], rmy[kUnroll], rmz[kUnroll];
+          float rfx[kUnroll], rfy[kUnroll], rfz[kUnroll];
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u)
-            a[u] = Ph::arg(tb[u].mx, tb[u].my, tb[u].mz, tb[u].fx, tb[u].fy, tb[u].fz, ux[j], uy[j], uz[j]);
+          for (int u = 0; u < kUnroll; ++u) {
+            rmx[u] = tb[u].mx; rmy[u] = tb[u].my; rmz[u] = tb[u].mz;
+            rfx[u] = tb[u].fx; rfy[u] = tb[u].fy; rfz[u] = tb[u].fz;
+          }
+          Ph::template args<kUnroll>(rmx, rmy, rmz, rfx, rfy, rfz, ux[j], uy[j], uz[j], a);
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) sn[u] = __builtin_amdgcn_sinf(a[u]);
 #pragma unroll

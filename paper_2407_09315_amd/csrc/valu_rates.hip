@@ -20,7 +20,7 @@
 
 constexpr int kIter = 2048;
 constexpr int kStreams = 16;
-constexpr int kOps = 26;
+constexpr int kOps = 28;
 
 // ops per stream step and their names
 const char* kNames[kOps] = {"v_fma_f32", "v_fmac_f32", "v_add_f32", "v_mul_f32", "v_mul_lo_u32",
@@ -30,8 +30,9 @@ const char* kNames[kOps] = {"v_fma_f32", "v_fmac_f32", "v_add_f32", "v_mul_f32",
                             "v_rndne_f32", "v_fract_f32", "v_cvt_f32_u32", "v_xad_u32",
                             "v_sin_f32 + 4 independent v_fma_f32", "4 v_mul_lo_u32 then 4 v_fma_f32",
                             "v_sin_f32 + 4 v_mul_lo_u32 + 4 v_fma_f32", "force term: sin cos 5 int 5 fma",
-                            "rho term: sin cos 5 int 2 fma"};
-const int kInstr[kOps] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 5, 5, 10, 1, 1, 1, 1, 1, 1, 5, 8, 9, 12, 9};
+                            "rho term: sin cos 5 int 2 fma", "v_mad_u64_u32",
+                            "rho term, mad_u64 phase: sin cos 4 int 2 fma"};
+const int kInstr[kOps] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 5, 5, 10, 1, 1, 1, 1, 1, 1, 5, 8, 9, 12, 9, 1, 8};
 
 template <int OP>
 __global__ __launch_bounds__(256) void rate_kernel(float* out, unsigned long long* clk, int n_out) {
@@ -117,6 +118,16 @@ __global__ __launch_bounds__(256) void rate_kernel(float* out, unsigned long lon
                        : "+v"(f0), "+v"(f1), "+v"(f2), "+v"(f3), "+v"(f4) : "v"(a), "v"(b));
         else
           asm volatile("v_fma_f32 %0, %0, %2, %3\n v_fma_f32 %1, %1, %2, %3" : "+v"(f0), "+v"(f1) : "v"(a), "v"(b));
+      }
+      if (OP == 26) asm volatile("v_mad_u64_u32 %0, vcc, %1, %2, %0" : "+v"(z[j]) : "v"(ia), "v"(ib) : "vcc");
+      if (OP == 27) {
+        // the rho term with the phase as mul_lo and two 64-bit-accumulating multiply-adds
+        // (the low word of a u32 x u32 + u64 product is the phase mod 2^32)
+        asm volatile("v_sin_f32 %0, %0" : "+v"(x[j]));
+        asm volatile("v_cos_f32 %0, %0" : "+v"(x[(j + 1) % kStreams]));
+        asm volatile("v_mul_lo_u32 %0, %0, %3\n v_mad_u64_u32 %1, vcc, %3, %4, %1\n v_mad_u64_u32 %2, vcc, %3, %4, %2\n v_alignbit_b32 %0, %4, %0, 9"
+                     : "+v"(y0), "+v"(z[j]), "+v"(z[(j + 8) % kStreams]) : "v"(ia), "v"(ib) : "vcc");
+        asm volatile("v_fma_f32 %0, %0, %2, %3\n v_fma_f32 %1, %1, %2, %3" : "+v"(f0), "+v"(f1) : "v"(a), "v"(b));
       }
       if (OP == 14) {
         asm volatile("v_sin_f32 %0, %0" : "+v"(x[j]));
@@ -215,6 +226,8 @@ int main() {
   time_op<23>(blocks, lds, f, clk, n_out, h, &ms[23], &ghz[23]);
   time_op<24>(blocks, lds, f, clk, n_out, h, &ms[24], &ghz[24]);
   time_op<25>(blocks, lds, f, clk, n_out, h, &ms[25], &ghz[25]);
+  time_op<26>(blocks, lds, f, clk, n_out, h, &ms[26], &ghz[26]);
+  time_op<27>(blocks, lds, f, clk, n_out, h, &ms[27], &ghz[27]);
   std::printf("%d waves per SIMD, %d independent streams per lane, %d steps\n", wps, kStreams, kIter);
   std::printf("%-36s %8s %8s %14s %14s %12s\n", "instruction (per step)", "ms", "GHz", "ops/CU/clk@2.4", "ops/CU/clk@own",
               "cyc/wave64");
