@@ -66,12 +66,14 @@ struct ForceItem {
 // Kernel variant tables (the autotuner picks one entry of each).
 // rho: particles per lane, wave vectors per chunk, at most krange wave vectors per work item
 // (a system's wave vectors are cut into ranges of whole chunks whose counts differ by <= 1),
-// waves per block: 4 (one item per wave) or 16 (one block per CU sharing single-chunk
-// items through LDS; krange is then one chunk)
+// waves per block: 4 (one item per wave), 16 (one block per CU sharing single-chunk
+// items through LDS; krange is then one chunk) or 1 for the k-lane layout (one item per
+// 256-thread block, wave vectors across the lanes; "wave vectors per chunk" is then the
+// wave vectors per lane)
 struct RhoVariant { int npl; int kc; int krange; int wpb; };
 struct ForceVariant { int nplf; };                       // particles per lane (256-thread blocks)
 
-constexpr int kNumRhoVariantsF32 = 9;
+constexpr int kNumRhoVariantsF32 = 10;
 constexpr int kNumRhoVariantsF64 = 8;
 constexpr int kNumForceVariants = 3;
 extern const RhoVariant kRhoVariantsF32[kNumRhoVariantsF32];

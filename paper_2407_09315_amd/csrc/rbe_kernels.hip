@@ -34,7 +34,10 @@ namespace rbe {
 // {particles per lane, wave vectors per chunk, wave vectors per work item}
 const RhoVariant kRhoVariantsF32[kNumRhoVariantsF32] = {
     {8, 8, 56, 4}, {8, 8, 40, 4}, {8, 8, 32, 4}, {8, 8, 104, 4}, {16, 8, 56, 4},
-    {8, 4, 28, 4}, {8, 4, 12, 4}, {8, 8, 8, 16}, {8, 4, 4, 16}};
+    {8, 4, 28, 4}, {8, 4, 12, 4}, {8, 8, 8, 16}, {8, 4, 4, 16},
+    // k-lane layout (wpb 1: one item per 256-thread block): 5 wave vectors per lane, 3 x 21
+    // lanes, so an item covers up to 105 wave vectors
+    {8, 5, 105, 1}};
 const RhoVariant kRhoVariantsF64[kNumRhoVariantsF64] = {
     {8, 4, 52, 4}, {8, 2, 50, 4}, {8, 2, 34, 4}, {8, 4, 36, 4}, {8, 4, 100, 4},
     {4, 4, 100, 4}, {4, 8, 104, 4}, {4, 4, 4, 16}};
@@ -80,6 +83,9 @@ template <> __device__ inline void keep_u64<1>(uint64_t (&t)[1]) { asm("" : "+v"
 template <> __device__ inline void keep_u64<2>(uint64_t (&t)[2]) { asm("" : "+v"(t[0]), "+v"(t[1])); }
 template <> __device__ inline void keep_u64<4>(uint64_t (&t)[4]) {
   asm("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]));
+}
+template <> __device__ inline void keep_u64<5>(uint64_t (&t)[5]) {
+  asm("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]));
 }
 template <> __device__ inline void keep_u64<8>(uint64_t (&t)[8]) {
   asm("" : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]), "+v"(t[5]), "+v"(t[6]), "+v"(t[7]));
@@ -509,6 +515,128 @@ __global__ __launch_bounds__(64 * WPB) void rho_f32_kernel(WsView w, const doubl
           part[2 * (kl * sd.ntiles + it.tile) + comp] = (double)acc[0];
         }
       }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ rho pass, k-lane layout
+
+// The rho pass with wave vectors across the lanes instead of particles.  A 256-thread block
+// takes one (tile, k-range) item: the tile's kKlTile particles are staged in LDS as fixed-
+// point (or FP32) fractions and FP32 charges, and each wave takes a quarter of them.  Lane
+// (g, kl) of a wave, g < G, kl < 64 / G, holds the KPL wave vectors k0 + kl + (64 / G) c and
+// sums them over particles g, g + G, ... of the wave's quarter, reading each particle from
+// LDS once for its KPL terms.  No value crosses lanes until the item is done; then the
+// 4 G partial sums of each (wave vector, component) are added in a fixed order in FP64.
+// This takes the per-chunk wave reduce-scatter and the particle registers out of the
+// inner loop.  Forward pass only: the adjoint pass B1 and the phase cache run the
+// per-wave kernel over the same items and tiles.
+constexpr int kKlTile = 512;   // particles per tile (64 lanes x 8, as the per-wave kernels)
+
+template <bool FPH> struct KlParticle;
+template <> struct KlParticle<false> { uint32_t ux, uy, uz; float q; };
+template <> struct KlParticle<true> { float ux, uy, uz; float q; };
+
+template <int G, int KPL, bool FPH>
+__global__ __launch_bounds__(256) void rho_klane_kernel(WsView w, const double* __restrict__ x,
+                                                       const double* __restrict__ y,
+                                                       const double* __restrict__ z,
+                                                       const double* __restrict__ q,
+                                                       const int32_t* __restrict__ m, int32_t n_items) {
+  constexpr int KL = 64 / G;              // k-lanes per wave
+  constexpr int PW = kKlTile / 4;         // particles per wave
+  constexpr int STEPS = (PW + G - 1) / G; // particle steps of every lane
+  constexpr int PWP = STEPS * G;          // a wave's LDS slots: its particles, then zero ones
+  using Ph = Phase<FPH>;
+  using Pt = KlParticle<FPH>;
+  static_assert(sizeof(Pt) == 16, "one 16-byte LDS read per particle");
+  __shared__ __align__(16) Pt tile[4 * PWP];
+  __shared__ float red[4][G][2 * KPL][KL];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int kl = lane % KL;
+  const int g = lane / KL;                // G for the 64 - G KL idle lanes
+  for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const RhoItem it = w.rho_items[__builtin_amdgcn_readfirstlane(item)];
+    const SysDesc sd = w.sys[it.sys];
+    const int first = it.tile * kKlTile;
+    const int cnt = min(kKlTile, sd.n - first);
+    const double invL = 1.0 / sd.L;
+    // this lane's wave vectors (zero past the item's end or on idle lanes)
+    int32_t mx[KPL], my[KPL], mz[KPL];
+    float fmx[KPL], fmy[KPL], fmz[KPL];
+#pragma unroll
+    for (int c = 0; c < KPL; ++c) {
+      const int kk = kl + KL * c;
+      const bool ok = g < G && kk < it.nk;
+      const int64_t gk = sd.k_off + it.k0 + min(kk, max(it.nk - 1, 0));
+      const int32_t a = m[3 * gk], b = m[3 * gk + 1], d = m[3 * gk + 2];
+      mx[c] = ok ? a : 0;
+      my[c] = ok ? b : 0;
+      mz[c] = ok ? d : 0;
+      fmx[c] = (float)mx[c];
+      fmy[c] = (float)my[c];
+      fmz[c] = (float)mz[c];
+    }
+    __syncthreads();   // the previous item's readers of tile and red are done
+    for (int i = tid; i < 4 * PWP; i += 256) {
+      // slot i is particle (i / PWP) PW + i % PWP of the tile, or a zero pad slot
+      const int wv = i / PWP, sl = i % PWP;
+      const int pi = wv * PW + sl;
+      Pt v;
+      if (sl < PW && pi < cnt) {
+        const int64_t gi = sd.n_off + first + pi;
+        v.ux = Ph::coord(x[gi], invL);
+        v.uy = Ph::coord(y[gi], invL);
+        v.uz = Ph::coord(z[gi], invL);
+        v.q = (float)q[gi];
+      } else {
+        v.ux = v.uy = v.uz = 0;
+        v.q = 0.0f;
+      }
+      tile[i] = v;
+    }
+    __syncthreads();
+    float acc[2 * KPL];
+#pragma unroll
+    for (int c = 0; c < 2 * KPL; ++c) acc[c] = 0.0f;
+    if (g < G) {
+      // the same number of steps on every lane (zero slots pad the last one); the next
+      // particle is read from LDS while this one's terms are computed
+      const Pt* tp = tile + wave * PWP + g;
+      Pt nxt = tp[0];
+      for (int j = 0; j < STEPS; ++j) {
+        const Pt v = nxt;
+        if (j + 1 < STEPS) nxt = tp[(j + 1) * G];
+        float a[KPL], sn[KPL], cs[KPL];
+        Ph::template args<KPL>(mx, my, mz, fmx, fmy, fmz, v.ux, v.uy, v.uz, a);
+#pragma unroll
+        for (int c = 0; c < KPL; ++c) sn[c] = __builtin_amdgcn_sinf(a[c]);
+#pragma unroll
+        for (int c = 0; c < KPL; ++c) cs[c] = __builtin_amdgcn_cosf(a[c]);
+#pragma unroll
+        for (int c = 0; c < KPL; ++c) {
+          acc[c] = fmaf(v.q, cs[c], acc[c]);
+          acc[KPL + c] = fmaf(v.q, sn[c], acc[KPL + c]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 2 * KPL; ++c) red[wave][g][c][kl] = acc[c];
+    }
+    __syncthreads();
+    // output o = (wave vector kk, component): the 4 G partial sums in a fixed order
+    double* part = w.partials + 2 * sd.part_off;
+    for (int o = tid; o < 2 * it.nk; o += 256) {
+      const int kk = o >> 1, comp = o & 1;
+      const int c = kk / KL, r = kk % KL;
+      double sum = 0.0;
+#pragma unroll
+      for (int wv = 0; wv < 4; ++wv)
+#pragma unroll
+        for (int gg = 0; gg < G; ++gg) sum += (double)red[wv][gg][comp * KPL + c][r];
+      const int64_t kidx = it.k0 + kk;
+      part[2 * (kidx * sd.ntiles + it.tile) + comp] = sum;
     }
   }
 }
@@ -1359,11 +1487,31 @@ void launch_rho_f64_t(const LaunchShape& s, const WsView& w, const double* x, co
                      s.n_total, s.n_rho_items);
 }
 
+// k-lane rho pass: one 256-thread block per item (rho_grid_cap counts waves, four a block)
+template <int G, int KPL, bool FPH>
+void launch_rho_klane_t(const LaunchShape& s, const WsView& w, const double* x, const double* y,
+                        const double* z, const double* q, const int32_t* m, hipStream_t st) {
+  int32_t blocks = s.n_rho_items;
+  if (s.rho_grid_cap > 0) blocks = std::min<int32_t>(blocks, std::max<int32_t>((s.rho_grid_cap + 3) / 4, 1));
+  hipLaunchKernelGGL((rho_klane_kernel<G, KPL, FPH>), dim3((unsigned)std::max<int32_t>(blocks, 1)), dim3(256), 0,
+                     st, w, x, y, z, q, m, s.n_rho_items);
+}
+
 // Particle-tile pass over every (tile, k-range) item; VJP selects adjoint pass B1.
 template <bool CACHE, bool VJP, bool FPH>
 void tile_pass_f32(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                    const double* z, const double* q, const int32_t* m, const float* g, hipStream_t st) {
   switch (s.rv.wpb * 10000 + s.rv.npl * 100 + s.rv.kc) {
+    case 10805:
+      // the k-lane layout (3 x 21 lanes, 5 wave vectors each) computes the forward pass; the
+      // adjoint and the phase cache use the per-wave kernel on the same 512-particle tiles
+      if constexpr (!CACHE && !VJP) {
+        static_assert(kKlTile == 64 * 8, "the fallback kernel's tile");
+        launch_rho_klane_t<3, 5, FPH>(s, w, x, y, z, q, m, st);
+      } else {
+        launch_rho_f32_t<8, 8, CACHE, VJP, FPH, 4>(s, w, x, y, z, q, m, g, st);
+      }
+      break;
     case 160808: launch_rho_f32_t<8, 8, CACHE, VJP, FPH, 16>(s, w, x, y, z, q, m, g, st); break;
     case 160804: launch_rho_f32_t<8, 4, CACHE, VJP, FPH, 16>(s, w, x, y, z, q, m, g, st); break;
     case 41608: launch_rho_f32_t<16, 8, CACHE, VJP, FPH, 4>(s, w, x, y, z, q, m, g, st); break;

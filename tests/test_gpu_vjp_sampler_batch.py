@@ -24,9 +24,9 @@ from parity_util import FP32_TOL, dev, force_err, note, particles, rel, to_dev
 pytestmark = pytest.mark.gpu
 
 
-def _vjp_case(s, alpha, P, precision, seed=2005):
+def _vjp_case(s, alpha, P, precision, seed=2005, tiles=None):
     m, w, _ = rbe_sample_k(seed, 0, s.L, alpha, P)
-    plan = Plan(Batch.single(s.n, P, s.L, alpha), precision=precision, device=dev())
+    plan = Plan(Batch.single(s.n, P, s.L, alpha), precision=precision, device=dev(), tiles=tiles)
     X = particles(s)
     mt, wt = to_dev(m, torch.int32), to_dev(w)
     F, U, rho = plan.forward(*X, mt, wt)
@@ -52,6 +52,18 @@ def test_vjp_vs_oracle_small(precision):
     note(f"  dL/dr {er:.2e}  dL/dq {eq:.2e}")
     tol = 1e-12 if precision == "fp64" else FP32_TOL
     assert er < tol and eq < tol
+
+
+@pytest.mark.parametrize("precision", ["fp32_mixed", "fp32"])
+def test_vjp_klane_variant(precision):
+    """With the k-lane rho layout selected, pass B1 runs the per-wave kernel on its items."""
+    s, alpha, P = ri.c1_small()
+    note(f"case vjp c1 k-lane {precision}")
+    plan, m, w, X, mt, wt, Fref, F, gF, gr, gq = _vjp_case(s, alpha, P, precision, tiles=(9, 0))
+    gr_ref, gq_ref = oracle.vjp(s.x, s.y, s.z, s.q, m, w, s.L, 1.0, gF.double().cpu().numpy())
+    er, eq = _grad_err(gr, gr_ref), _grad_err(gq, gq_ref)
+    note(f"  dL/dr {er:.2e}  dL/dq {eq:.2e}")
+    assert er < FP32_TOL and eq < FP32_TOL
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
