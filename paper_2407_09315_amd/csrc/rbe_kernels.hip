@@ -529,20 +529,23 @@ __global__ __launch_bounds__(64 * WPB) void rho_f32_kernel(WsView w, const doubl
 // LDS once for its KPL terms.  No value crosses lanes until the item is done; then the
 // 4 G partial sums of each (wave vector, component) are added in a fixed order in FP64.
 // This takes the per-chunk wave reduce-scatter and the particle registers out of the
-// inner loop.  Forward pass only: the adjoint pass B1 and the phase cache run the
-// per-wave kernel over the same items and tiles.
+// inner loop.  With VJP it forms X + iY of the adjoint pass B1, the per-term weight
+// q_i (gF_i . m_l) coming from the staged q_i gF_i.  The phase cache runs the per-wave
+// kernel over the same items and tiles.
 constexpr int kKlTile = 512;   // particles per tile (64 lanes x 8, as the per-wave kernels)
 
 template <bool FPH> struct KlParticle;
 template <> struct KlParticle<false> { uint32_t ux, uy, uz; float q; };
 template <> struct KlParticle<true> { float ux, uy, uz; float q; };
 
-template <int G, int KPL, bool FPH>
+template <int G, int KPL, bool VJP, bool FPH>
 __global__ __launch_bounds__(256) void rho_klane_kernel(WsView w, const double* __restrict__ x,
                                                        const double* __restrict__ y,
                                                        const double* __restrict__ z,
                                                        const double* __restrict__ q,
-                                                       const int32_t* __restrict__ m, int32_t n_items) {
+                                                       const int32_t* __restrict__ m,
+                                                       const float* __restrict__ gF, int64_t n_total,
+                                                       int32_t n_items) {
   constexpr int KL = 64 / G;              // k-lanes per wave
   constexpr int PW = kKlTile / 4;         // particles per wave
   constexpr int STEPS = (PW + G - 1) / G; // particle steps of every lane
@@ -551,6 +554,7 @@ __global__ __launch_bounds__(256) void rho_klane_kernel(WsView w, const double* 
   using Pt = KlParticle<FPH>;
   static_assert(sizeof(Pt) == 16, "one 16-byte LDS read per particle");
   __shared__ __align__(16) Pt tile[4 * PWP];
+  __shared__ __align__(16) float4 tgw[VJP ? 4 * PWP : 1];   // q gF of each slot (VJP)
   __shared__ float red[4][G][2 * KPL][KL];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -585,17 +589,20 @@ __global__ __launch_bounds__(256) void rho_klane_kernel(WsView w, const double* 
       const int wv = i / PWP, sl = i % PWP;
       const int pi = wv * PW + sl;
       Pt v;
+      float4 qg = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if (sl < PW && pi < cnt) {
         const int64_t gi = sd.n_off + first + pi;
         v.ux = Ph::coord(x[gi], invL);
         v.uy = Ph::coord(y[gi], invL);
         v.uz = Ph::coord(z[gi], invL);
         v.q = (float)q[gi];
+        if (VJP) qg = make_float4(v.q * gF[gi], v.q * gF[n_total + gi], v.q * gF[2 * n_total + gi], 0.0f);
       } else {
         v.ux = v.uy = v.uz = 0;
         v.q = 0.0f;
       }
       tile[i] = v;
+      if (VJP) tgw[i] = qg;
     }
     __syncthreads();
     float acc[2 * KPL];
@@ -605,10 +612,13 @@ __global__ __launch_bounds__(256) void rho_klane_kernel(WsView w, const double* 
       // the same number of steps on every lane (zero slots pad the last one); the next
       // particle is read from LDS while this one's terms are computed
       const Pt* tp = tile + wave * PWP + g;
+      const float4* gp = tgw + (VJP ? wave * PWP + g : 0);
       Pt nxt = tp[0];
       for (int j = 0; j < STEPS; ++j) {
         const Pt v = nxt;
         if (j + 1 < STEPS) nxt = tp[(j + 1) * G];
+        float4 qg = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (VJP) qg = gp[j * G];
         float a[KPL], sn[KPL], cs[KPL];
         Ph::template args<KPL>(mx, my, mz, fmx, fmy, fmz, v.ux, v.uy, v.uz, a);
 #pragma unroll
@@ -617,8 +627,10 @@ __global__ __launch_bounds__(256) void rho_klane_kernel(WsView w, const double* 
         for (int c = 0; c < KPL; ++c) cs[c] = __builtin_amdgcn_cosf(a[c]);
 #pragma unroll
         for (int c = 0; c < KPL; ++c) {
-          acc[c] = fmaf(v.q, cs[c], acc[c]);
-          acc[KPL + c] = fmaf(v.q, sn[c], acc[KPL + c]);
+          float wt = v.q;
+          if (VJP) wt = fmaf(qg.x, fmx[c], fmaf(qg.y, fmy[c], qg.z * fmz[c]));
+          acc[c] = fmaf(wt, cs[c], acc[c]);
+          acc[KPL + c] = fmaf(wt, sn[c], acc[KPL + c]);
         }
       }
 #pragma unroll
@@ -1488,13 +1500,13 @@ void launch_rho_f64_t(const LaunchShape& s, const WsView& w, const double* x, co
 }
 
 // k-lane rho pass: one 256-thread block per item (rho_grid_cap counts waves, four a block)
-template <int G, int KPL, bool FPH>
+template <int G, int KPL, bool VJP, bool FPH>
 void launch_rho_klane_t(const LaunchShape& s, const WsView& w, const double* x, const double* y,
-                        const double* z, const double* q, const int32_t* m, hipStream_t st) {
+                        const double* z, const double* q, const int32_t* m, const float* gF, hipStream_t st) {
   int32_t blocks = s.n_rho_items;
   if (s.rho_grid_cap > 0) blocks = std::min<int32_t>(blocks, std::max<int32_t>((s.rho_grid_cap + 3) / 4, 1));
-  hipLaunchKernelGGL((rho_klane_kernel<G, KPL, FPH>), dim3((unsigned)std::max<int32_t>(blocks, 1)), dim3(256), 0,
-                     st, w, x, y, z, q, m, s.n_rho_items);
+  hipLaunchKernelGGL((rho_klane_kernel<G, KPL, VJP, FPH>), dim3((unsigned)std::max<int32_t>(blocks, 1)), dim3(256),
+                     0, st, w, x, y, z, q, m, gF, s.n_total, s.n_rho_items);
 }
 
 // Particle-tile pass over every (tile, k-range) item; VJP selects adjoint pass B1.
@@ -1503,11 +1515,11 @@ void tile_pass_f32(const LaunchShape& s, const WsView& w, const double* x, const
                    const double* z, const double* q, const int32_t* m, const float* g, hipStream_t st) {
   switch (s.rv.wpb * 10000 + s.rv.npl * 100 + s.rv.kc) {
     case 10805:
-      // the k-lane layout (3 x 21 lanes, 5 wave vectors each) computes the forward pass; the
-      // adjoint and the phase cache use the per-wave kernel on the same 512-particle tiles
-      if constexpr (!CACHE && !VJP) {
+      // the k-lane layout (3 x 21 lanes, 5 wave vectors each) computes the forward pass and
+      // pass B1; the phase cache uses the per-wave kernel on the same 512-particle tiles
+      if constexpr (!CACHE) {
         static_assert(kKlTile == 64 * 8, "the fallback kernel's tile");
-        launch_rho_klane_t<3, 5, FPH>(s, w, x, y, z, q, m, st);
+        launch_rho_klane_t<3, 5, VJP, FPH>(s, w, x, y, z, q, m, g, st);
       } else {
         launch_rho_f32_t<8, 8, CACHE, VJP, FPH, 4>(s, w, x, y, z, q, m, g, st);
       }
