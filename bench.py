@@ -95,7 +95,8 @@ def run_form(torch, plan_cls, batch_cls, X, L, alpha, P, precision, phase_mode, 
         wall_eval = (time.perf_counter() - t0) / steps
         out = {"wall_s": min(wall_graph, wall_eval), "wall_graph_s": wall_graph, "wall_evaluate_s": wall_eval,
                "m": g.m.cpu().numpy(), "w": g.w.cpu().numpy(), "F": g.F.double().cpu().numpy(),
-               "U": float(g.U.cpu()[0]), "rho": g.rho.cpu().numpy(), "tiles": plan.tiles()}
+               "U": float(g.U.cpu()[0]), "rho": g.rho.cpu().numpy(), "tiles": plan.tiles(),
+               "rho_kernel": rho_kernel_name(plan)}
         # kernel timing: the same step as eager calls, events around each pass's kernel
         m = torch.empty_like(g.m)
         w = torch.empty_like(g.w)
@@ -172,6 +173,7 @@ def main():
     f32, f64 = res["fp32"], res["fp64"]
     value = terms / f32["wall_s"] / 1e9
     dom = "rho" if f32["t_rho_s"] >= f32["t_force_s"] else "force"
+    rho_name = f32["rho_kernel"]
     t_dom = f32["t_rho_s"] if dom == "rho" else f32["t_force_s"]
     flop = FLOP_RHO if dom == "rho" else FLOP_FORCE
     achieved = flop * terms / t_dom / 1e12
@@ -204,12 +206,12 @@ def main():
         "fp32_over_fp64_speedup": round(f64["wall_s"] / f32["wall_s"], 3),
         "fp32_kernels_ms": {"rho_kernel": round(f32["t_rho_s"] * 1e3, 4), "force_kernel": round(f32["t_force_s"] * 1e3, 4),
                             "tiles": f32["tiles"]},
-        "roofline": {"bound": "alu", "kernel": "rho_f32_kernel" if dom == "rho" else "force_f32_kernel",
+        "roofline": {"bound": "alu", "kernel": rho_name if dom == "rho" else "force_f32_kernel",
                      "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4),
-                     "traffic": traffic_from_profile("rho_f32_kernel" if dom == "rho" else "force_f32_kernel"),
+                     "traffic": traffic_from_profile(rho_name if dom == "rho" else "force_f32_kernel"),
                      "flop_equivalents_per_term": flop, "terms_per_launch": terms,
-                     "other_pass": {"kernel": "force_f32_kernel" if dom == "rho" else "rho_f32_kernel",
+                     "other_pass": {"kernel": "force_f32_kernel" if dom == "rho" else rho_name,
                                     "frac": round((FLOP_FORCE if dom == "rho" else FLOP_RHO) * terms /
                                                   (f32["t_force_s"] if dom == "rho" else f32["t_rho_s"]) / PEAK_FLOP, 4)},
                      "whole_evaluation_frac": round((FLOP_RHO + FLOP_FORCE) * terms / f32["wall_s"] / PEAK_FLOP, 4)},
@@ -235,6 +237,14 @@ def profile_run(torch, Plan, Batch, X, s, alpha, P, dev):
         dst.copy_(src)
     torch.cuda.synchronize()
     log("profile copy: 3 x 256 MiB")
+
+
+def rho_kernel_name(plan):
+    """Name of the rho kernel the plan's selected variant launches (as rocprofv3 reports it)."""
+    if plan.precision == "fp64":
+        return "rho_f64_kernel"
+    info = plan.rho_variant_info(plan.tiles()[0])
+    return "rho_klane_kernel" if info["waves_per_block"] == 1 else "rho_f32_kernel"
 
 
 def traffic_from_profile(kernel: str):

@@ -146,6 +146,21 @@ rbe_status rbe_plan_num_variants(const rbe_plan *plan, int32_t *n_rho, int32_t *
 rbe_status rbe_plan_get_tiles(const rbe_plan *plan, int32_t *rho_variant, int32_t *force_variant);
 
 /*
+ * Layout of rho variant `variant` of the plan's precision (0 <= variant < n_rho of
+ * rbe_plan_num_variants), written to the four host int32 outputs:
+ *   particles_per_lane: the tile is 64 x this many particles;
+ *   vectors_per_chunk: wave vectors per inner-loop chunk (per lane in the k-lane layout);
+ *   vectors_per_item: at most this many wave vectors per work item;
+ *   waves_per_block: 4 (one item per wave), 16 (one block per CU sharing single-chunk
+ *     items) or 1 (k-lane layout: one item per 256-thread block, wave vectors across
+ *     the lanes).
+ * RBE_EINVAL for a NULL pointer or a variant out of range.
+ */
+rbe_status rbe_plan_rho_variant_info(const rbe_plan *plan, int32_t variant, int32_t *particles_per_lane,
+                                     int32_t *vectors_per_chunk, int32_t *vectors_per_item,
+                                     int32_t *waves_per_block);
+
+/*
  * Persistent grids.  The rho-shaped passes run one wave per work item, four
  * waves per block; rho_cap > 0 launches at most rho_cap waves (rounded up to
  * whole blocks).  The force-shaped passes run one 256-thread block per work

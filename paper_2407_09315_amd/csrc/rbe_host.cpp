@@ -442,6 +442,19 @@ rbe_status rbe_plan_num_variants(const rbe_plan* p, int32_t* n_rho, int32_t* n_f
   return RBE_OK;
 }
 
+rbe_status rbe_plan_rho_variant_info(const rbe_plan* p, int32_t variant, int32_t* npl, int32_t* kc,
+                                     int32_t* krange, int32_t* wpb) {
+  if (!p || !npl || !kc || !krange || !wpb) return fail(RBE_EINVAL, "NULL argument");
+  const int nr = p->precision == RBE_FP64 ? kNumRhoVariantsF64 : kNumRhoVariantsF32;
+  if (variant < 0 || variant >= nr) return fail(RBE_EINVAL, "rho variant %d out of range [0, %d)", variant, nr);
+  const RhoVariant& rv = p->precision == RBE_FP64 ? kRhoVariantsF64[variant] : kRhoVariantsF32[variant];
+  *npl = rv.npl;
+  *kc = rv.kc;
+  *krange = rv.krange;
+  *wpb = rv.wpb;
+  return RBE_OK;
+}
+
 rbe_status rbe_plan_get_tiles(const rbe_plan* p, int32_t* rv, int32_t* fv) {
   if (!p || !rv || !fv) return fail(RBE_EINVAL, "NULL argument");
   *rv = p->rho_variant;

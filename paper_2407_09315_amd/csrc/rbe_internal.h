@@ -73,7 +73,7 @@ struct ForceItem {
 struct RhoVariant { int npl; int kc; int krange; int wpb; };
 struct ForceVariant { int nplf; };                       // particles per lane (256-thread blocks)
 
-constexpr int kNumRhoVariantsF32 = 10;
+constexpr int kNumRhoVariantsF32 = 11;
 constexpr int kNumRhoVariantsF64 = 8;
 constexpr int kNumForceVariants = 3;
 extern const RhoVariant kRhoVariantsF32[kNumRhoVariantsF32];

@@ -36,8 +36,8 @@ const RhoVariant kRhoVariantsF32[kNumRhoVariantsF32] = {
     {8, 8, 56, 4}, {8, 8, 40, 4}, {8, 8, 32, 4}, {8, 8, 104, 4}, {16, 8, 56, 4},
     {8, 4, 28, 4}, {8, 4, 12, 4}, {8, 8, 8, 16}, {8, 4, 4, 16},
     // k-lane layout (wpb 1: one item per 256-thread block): 5 wave vectors per lane, 3 x 21
-    // lanes, so an item covers up to 105 wave vectors
-    {8, 5, 105, 1}};
+    // lanes, so an item covers up to 105 wave vectors; tiles of 512 and 256 particles
+    {8, 5, 105, 1}, {4, 5, 105, 1}};
 const RhoVariant kRhoVariantsF64[kNumRhoVariantsF64] = {
     {8, 4, 52, 4}, {8, 2, 50, 4}, {8, 2, 34, 4}, {8, 4, 36, 4}, {8, 4, 100, 4},
     {4, 4, 100, 4}, {4, 8, 104, 4}, {4, 4, 4, 16}};
@@ -522,7 +522,7 @@ __global__ __launch_bounds__(64 * WPB) void rho_f32_kernel(WsView w, const doubl
 // ------------------------------------------------------------------ rho pass, k-lane layout
 
 // The rho pass with wave vectors across the lanes instead of particles.  A 256-thread block
-// takes one (tile, k-range) item: the tile's kKlTile particles are staged in LDS as fixed-
+// takes one (tile, k-range) item: the tile's TILE particles are staged in LDS as fixed-
 // point (or FP32) fractions and FP32 charges, and each wave takes a quarter of them.  Lane
 // (g, kl) of a wave, g < G, kl < 64 / G, holds the KPL wave vectors k0 + kl + (64 / G) c and
 // sums them over particles g, g + G, ... of the wave's quarter, reading each particle from
@@ -531,14 +531,14 @@ __global__ __launch_bounds__(64 * WPB) void rho_f32_kernel(WsView w, const doubl
 // This takes the per-chunk wave reduce-scatter and the particle registers out of the
 // inner loop.  With VJP it forms X + iY of the adjoint pass B1, the per-term weight
 // q_i (gF_i . m_l) coming from the staged q_i gF_i.  The phase cache runs the per-wave
-// kernel over the same items and tiles.
-constexpr int kKlTile = 512;   // particles per tile (64 lanes x 8, as the per-wave kernels)
+// kernel over the same items and tiles.  TILE (512 or 256 particles) is 64 NPL of the
+// variant, the tile of the per-wave kernel with the same NPL.
 
 template <bool FPH> struct KlParticle;
 template <> struct KlParticle<false> { uint32_t ux, uy, uz; float q; };
 template <> struct KlParticle<true> { float ux, uy, uz; float q; };
 
-template <int G, int KPL, bool VJP, bool FPH>
+template <int TILE, int G, int KPL, bool VJP, bool FPH>
 __global__ __launch_bounds__(256) void rho_klane_kernel(WsView w, const double* __restrict__ x,
                                                        const double* __restrict__ y,
                                                        const double* __restrict__ z,
@@ -547,7 +547,7 @@ __global__ __launch_bounds__(256) void rho_klane_kernel(WsView w, const double* 
                                                        const float* __restrict__ gF, int64_t n_total,
                                                        int32_t n_items) {
   constexpr int KL = 64 / G;              // k-lanes per wave
-  constexpr int PW = kKlTile / 4;         // particles per wave
+  constexpr int PW = TILE / 4;            // particles per wave
   constexpr int STEPS = (PW + G - 1) / G; // particle steps of every lane
   constexpr int PWP = STEPS * G;          // a wave's LDS slots: its particles, then zero ones
   using Ph = Phase<FPH>;
@@ -564,8 +564,8 @@ __global__ __launch_bounds__(256) void rho_klane_kernel(WsView w, const double* 
   for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
     const RhoItem it = w.rho_items[__builtin_amdgcn_readfirstlane(item)];
     const SysDesc sd = w.sys[it.sys];
-    const int first = it.tile * kKlTile;
-    const int cnt = min(kKlTile, sd.n - first);
+    const int first = it.tile * TILE;
+    const int cnt = min(TILE, sd.n - first);
     const double invL = 1.0 / sd.L;
     // this lane's wave vectors (zero past the item's end or on idle lanes)
     int32_t mx[KPL], my[KPL], mz[KPL];
@@ -1500,12 +1500,12 @@ void launch_rho_f64_t(const LaunchShape& s, const WsView& w, const double* x, co
 }
 
 // k-lane rho pass: one 256-thread block per item (rho_grid_cap counts waves, four a block)
-template <int G, int KPL, bool VJP, bool FPH>
+template <int TILE, int G, int KPL, bool VJP, bool FPH>
 void launch_rho_klane_t(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                         const double* z, const double* q, const int32_t* m, const float* gF, hipStream_t st) {
   int32_t blocks = s.n_rho_items;
   if (s.rho_grid_cap > 0) blocks = std::min<int32_t>(blocks, std::max<int32_t>((s.rho_grid_cap + 3) / 4, 1));
-  hipLaunchKernelGGL((rho_klane_kernel<G, KPL, VJP, FPH>), dim3((unsigned)std::max<int32_t>(blocks, 1)), dim3(256),
+  hipLaunchKernelGGL((rho_klane_kernel<TILE, G, KPL, VJP, FPH>), dim3((unsigned)std::max<int32_t>(blocks, 1)), dim3(256),
                      0, st, w, x, y, z, q, m, gF, s.n_total, s.n_rho_items);
 }
 
@@ -1515,13 +1515,15 @@ void tile_pass_f32(const LaunchShape& s, const WsView& w, const double* x, const
                    const double* z, const double* q, const int32_t* m, const float* g, hipStream_t st) {
   switch (s.rv.wpb * 10000 + s.rv.npl * 100 + s.rv.kc) {
     case 10805:
+    case 10405:
       // the k-lane layout (3 x 21 lanes, 5 wave vectors each) computes the forward pass and
-      // pass B1; the phase cache uses the per-wave kernel on the same 512-particle tiles
+      // pass B1; the phase cache uses the per-wave kernel on the same tiles
       if constexpr (!CACHE) {
-        static_assert(kKlTile == 64 * 8, "the fallback kernel's tile");
-        launch_rho_klane_t<3, 5, VJP, FPH>(s, w, x, y, z, q, m, g, st);
+        if (s.rv.npl == 8) launch_rho_klane_t<512, 3, 5, VJP, FPH>(s, w, x, y, z, q, m, g, st);
+        else launch_rho_klane_t<256, 3, 5, VJP, FPH>(s, w, x, y, z, q, m, g, st);
       } else {
-        launch_rho_f32_t<8, 8, CACHE, VJP, FPH, 4>(s, w, x, y, z, q, m, g, st);
+        if (s.rv.npl == 8) launch_rho_f32_t<8, 8, CACHE, VJP, FPH, 4>(s, w, x, y, z, q, m, g, st);
+        else launch_rho_f32_t<4, 8, CACHE, VJP, FPH, 4>(s, w, x, y, z, q, m, g, st);
       }
       break;
     case 160808: launch_rho_f32_t<8, 8, CACHE, VJP, FPH, 16>(s, w, x, y, z, q, m, g, st); break;

@@ -215,6 +215,14 @@ class Plan:
         check(self.lib.rbe_plan_num_variants(self.handle, ctypes.byref(a), ctypes.byref(b)), "rbe_plan_num_variants")
         return a.value, b.value
 
+    def rho_variant_info(self, variant: int) -> dict:
+        """Layout of a rho variant (rbe_plan_rho_variant_info); waves_per_block 1 is the k-lane layout."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        check(self.lib.rbe_plan_rho_variant_info(self.handle, int(variant), *[ctypes.byref(x) for x in v]),
+              "rbe_plan_rho_variant_info")
+        return dict(zip(("particles_per_lane", "vectors_per_chunk", "vectors_per_item", "waves_per_block"),
+                        (x.value for x in v)))
+
     @property
     def force_dtype(self):
         return torch.float64 if self.precision == "fp64" else torch.float32

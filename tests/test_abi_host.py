@@ -100,6 +100,27 @@ def test_plan_validation():
         lib.rbe_plan_destroy(h)
 
 
+def test_rho_variant_info():
+    """Every rho variant reports a layout the kernels implement; out-of-range indices are refused."""
+    lib = _lib.load()
+    for prec in (_lib.RBE_FP64, _lib.RBE_FP32_MIXED):
+        st, h = _create(1, [0, 10], [0, 5], [3.0], [1.0], prec=prec)
+        assert st == 0
+        nr, nf = ctypes.c_int32(), ctypes.c_int32()
+        assert lib.rbe_plan_num_variants(h, ctypes.byref(nr), ctypes.byref(nf)) == 0
+        v = [ctypes.c_int32() for _ in range(4)]
+        for r in range(nr.value):
+            assert lib.rbe_plan_rho_variant_info(h, r, *[ctypes.byref(x) for x in v]) == 0
+            npl, kc, krange, wpb = (x.value for x in v)
+            assert wpb in (1, 4, 16) and npl in (4, 8, 16) and 1 <= kc <= krange
+            if wpb == 1:
+                assert prec != _lib.RBE_FP64 and krange == 21 * kc   # 3 x 21 lanes, kc vectors each
+        for bad in (-1, nr.value):
+            assert lib.rbe_plan_rho_variant_info(h, bad, *[ctypes.byref(x) for x in v]) == _lib.RBE_EINVAL
+        assert lib.rbe_plan_rho_variant_info(h, 0, None, None, None, None) == _lib.RBE_EINVAL
+        lib.rbe_plan_destroy(h)
+
+
 def test_fp32_phase_box_guard():
     """RBE_FP32 phases are refused once the spread of sampled m, L sqrt(2 alpha) / (2 pi), exceeds 16."""
     lib = _lib.load()

@@ -87,25 +87,29 @@ def test_all_variants(precision):
             _check("c1 variants", s, alpha, P, 2001, precision, tiles=(rv, fv))
 
 
-# the k-lane rho layout: the last FP32 rho variant (5 wave vectors on each of 3 x 21 lanes,
-# one (tile, k-range) item per block, at most 105 wave vectors per item)
+# the k-lane rho layouts: the last two FP32 rho variants (5 wave vectors on each of 3 x 21
+# lanes, one (tile, k-range) item per block, at most 105 wave vectors per item; tiles of
+# 512 and 256 particles)
 KLANE = 9
+KLANE_256 = 10
 
 
 @pytest.mark.parametrize("precision", ["fp32_mixed", "fp32"])
+@pytest.mark.parametrize("rv", [KLANE, KLANE_256])
 @pytest.mark.parametrize("n,P", [(1300, 250), (511, 105), (2049, 106), (64, 3)])
-def test_klane_layout(n, P, precision):
+def test_klane_layout(n, P, rv, precision):
     """Several k-ranges per tile, a short last range, ragged and single tiles."""
     plan = Plan(Batch.single(n, P, 11.0, 0.35), precision=precision, device=dev())
-    assert plan.num_variants()[0] == KLANE + 1
+    assert plan.num_variants()[0] == KLANE_256 + 1
     s = ri.random_charges(n, 11.0, 70 + n)
-    _check(f"k-lane n={n}", s, 0.35, P, 300 + P, precision, tiles=(KLANE, 0))
+    _check(f"k-lane{rv} n={n}", s, 0.35, P, 300 + P, precision, tiles=(rv, 0))
 
 
-def test_klane_layout_phase_cache():
-    """The phase cache with the k-lane variant selected runs the per-wave kernel on its items."""
+@pytest.mark.parametrize("rv", [KLANE, KLANE_256])
+def test_klane_layout_phase_cache(rv):
+    """The phase cache with a k-lane variant selected runs the per-wave kernel on its items."""
     s = ri.random_charges(1300, 11.0, 71)
-    _check("k-lane cached", s, 0.35, 250, 551, "fp32_mixed", phase_mode="cached", tiles=(KLANE, 0))
+    _check(f"k-lane{rv} cached", s, 0.35, 250, 551, "fp32_mixed", phase_mode="cached", tiles=(rv, 0))
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])

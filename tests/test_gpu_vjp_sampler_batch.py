@@ -55,11 +55,12 @@ def test_vjp_vs_oracle_small(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp32_mixed", "fp32"])
-def test_vjp_klane_variant(precision):
-    """With the k-lane rho layout selected, pass B1 runs the per-wave kernel on its items."""
+@pytest.mark.parametrize("rv", [9, 10])
+def test_vjp_klane_variant(rv, precision):
+    """With a k-lane rho layout selected, pass B1 runs in that layout."""
     s, alpha, P = ri.c1_small()
-    note(f"case vjp c1 k-lane {precision}")
-    plan, m, w, X, mt, wt, Fref, F, gF, gr, gq = _vjp_case(s, alpha, P, precision, tiles=(9, 0))
+    note(f"case vjp c1 k-lane{rv} {precision}")
+    plan, m, w, X, mt, wt, Fref, F, gF, gr, gq = _vjp_case(s, alpha, P, precision, tiles=(rv, 0))
     gr_ref, gq_ref = oracle.vjp(s.x, s.y, s.z, s.q, m, w, s.L, 1.0, gF.double().cpu().numpy())
     er, eq = _grad_err(gr, gr_ref), _grad_err(gq, gq_ref)
     note(f"  dL/dr {er:.2e}  dL/dq {eq:.2e}")
