@@ -163,8 +163,9 @@ rbe_status rbe_plan_rho_variant_info(const rbe_plan *plan, int32_t variant, int3
 /*
  * Persistent grids.  The rho-shaped passes run one wave per work item, four
  * waves per block (the k-lane rho variants: one four-wave block per item);
- * rho_cap > 0 launches at most rho_cap waves (rounded up to whole blocks).  The force-shaped passes run one 256-thread block per work
- * item; force_cap > 0 launches at most force_cap blocks.  Wave (block) j of a
+ * rho_cap > 0 launches at most rho_cap waves (rounded up to whole blocks).
+ * The force-shaped passes run one 256-thread block per work item;
+ * force_cap > 0 launches at most force_cap blocks.  Wave (block) j of a
  * capped grid of G takes items j, j + G, j + 2G, ...  0 (the default) launches
  * one wave (block) per item.  Results do not depend on the caps (each item
  * writes its own partial-sum slots).
