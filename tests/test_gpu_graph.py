@@ -86,6 +86,24 @@ def test_persistent_grid_caps_bitwise(precision, schedule):
         assert torch.equal(F0, F1) and torch.equal(U0, U1) and torch.equal(r0, r1), caps
 
 
+@pytest.mark.parametrize("precision", ["fp32_mixed", "fp32"])
+@pytest.mark.parametrize("rv", [9, 10])
+def test_klane_grid_caps_bitwise(precision, rv):
+    """The k-lane rho layouts under persistent grids (blocks striding over the items)."""
+    s, alpha, _ = ri.c4_differentiable()
+    P = 230                                   # three k-ranges per tile
+    m, w, _ = rbe_sample_k(8, 0, s.L, alpha, P)
+    X = particles(s)
+    mt, wt = to_dev(m, torch.int32), to_dev(w)
+    plan = Plan(Batch.single(s.n, P, s.L, alpha), precision=precision, tiles=(rv, 0))
+    F0, U0, r0 = plan.forward(*X, mt, wt)
+    for caps in [(37, 5), (1024, 256), (1, 1)]:
+        plan.set_grid_caps(*caps)
+        F1, U1, r1 = plan.forward(*X, mt, wt)
+        torch.cuda.synchronize()
+        assert torch.equal(F0, F1) and torch.equal(U0, U1) and torch.equal(r0, r1), caps
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
 def test_schedules_agree_bitwise(precision):
     """The per-(k, tile) partial sums do not depend on the schedule that computed them."""

@@ -153,14 +153,18 @@ def test_device_sampler_bit_exact():
         off += P
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
-def test_batched_equals_single(precision):
+# rho variants: the per-wave layout, and (FP32 forms) the two k-lane layouts
+BATCH_RHO = [("fp64", 0), ("fp32_mixed", 0), ("fp32", 0), ("fp32_mixed", 9), ("fp32_mixed", 10), ("fp32", 9)]
+
+
+@pytest.mark.parametrize("precision,rv", BATCH_RHO)
+def test_batched_equals_single(precision, rv):
     reps = ri.c5_replicas(B=10)
     systems = reps.systems + [ri.random_charges(3, 4.0, 1), ri.uniform_pm1(2000, 20.0, 2)]
     alphas = reps.alphas + [0.7, 0.2]
     ps = [100] * 10 + [5, 0]
     batch = Batch.from_sizes([s.n for s in systems], ps, [s.L for s in systems], alphas)
-    tiles = (0, 1)     # the same kernel variants for the batch and the single systems
+    tiles = (rv, 1)    # the same kernel variants for the batch and the single systems
     plan = Plan(batch, precision=precision, device=dev(), tiles=tiles)
     m, w = plan.sample_k_device(6000, 0)
     cat = [to_dev(np.concatenate([getattr(s, a) for s in systems])) for a in ("x", "y", "z", "q")]
