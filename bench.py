@@ -241,10 +241,10 @@ def profile_run(torch, Plan, Batch, X, s, alpha, P, dev):
 
 def rho_kernel_name(plan):
     """Name of the rho kernel the plan's selected variant launches (as rocprofv3 reports it)."""
+    klane = plan.rho_variant_info(plan.tiles()[0])["waves_per_block"] == 1
     if plan.precision == "fp64":
-        return "rho_f64_kernel"
-    info = plan.rho_variant_info(plan.tiles()[0])
-    return "rho_klane_kernel" if info["waves_per_block"] == 1 else "rho_f32_kernel"
+        return "rho_klane_f64_kernel" if klane else "rho_f64_kernel"
+    return "rho_klane_kernel" if klane else "rho_f32_kernel"
 
 
 def traffic_from_profile(kernel: str):

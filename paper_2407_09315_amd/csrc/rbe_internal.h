@@ -74,7 +74,7 @@ struct RhoVariant { int npl; int kc; int krange; int wpb; };
 struct ForceVariant { int nplf; };                       // particles per lane (256-thread blocks)
 
 constexpr int kNumRhoVariantsF32 = 11;
-constexpr int kNumRhoVariantsF64 = 8;
+constexpr int kNumRhoVariantsF64 = 9;
 constexpr int kNumForceVariants = 3;
 extern const RhoVariant kRhoVariantsF32[kNumRhoVariantsF32];
 extern const RhoVariant kRhoVariantsF64[kNumRhoVariantsF64];

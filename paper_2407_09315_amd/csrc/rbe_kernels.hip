@@ -40,7 +40,9 @@ const RhoVariant kRhoVariantsF32[kNumRhoVariantsF32] = {
     {8, 5, 105, 1}, {4, 5, 105, 1}};
 const RhoVariant kRhoVariantsF64[kNumRhoVariantsF64] = {
     {8, 4, 52, 4}, {8, 2, 50, 4}, {8, 2, 34, 4}, {8, 4, 36, 4}, {8, 4, 100, 4},
-    {4, 4, 100, 4}, {4, 8, 104, 4}, {4, 4, 4, 16}};
+    {4, 4, 100, 4}, {4, 8, 104, 4}, {4, 4, 4, 16},
+    // k-lane layout (wpb 1): 5 wave vectors on each of 3 x 21 lanes, 512-particle tiles
+    {8, 5, 105, 1}};
 const ForceVariant kForceVariants[kNumForceVariants] = {{1}, {2}, {4}};
 
 namespace {
@@ -647,6 +649,115 @@ __global__ __launch_bounds__(256) void rho_klane_kernel(WsView w, const double* 
       for (int wv = 0; wv < 4; ++wv)
 #pragma unroll
         for (int gg = 0; gg < G; ++gg) sum += (double)red[wv][gg][comp * KPL + c][r];
+      const int64_t kidx = it.k0 + kk;
+      part[2 * (kidx * sd.ntiles + it.tile) + comp] = sum;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ rho pass, FP64 k-lane
+
+// The k-lane layout of rho_klane_kernel in FP64: lane (g, kl) sums its KPL wave vectors
+// over particles g, g + G, ... of its wave's quarter of the tile, from fractional
+// coordinates in table units staged in LDS, with the table form of sin/cos.  At the end of
+// an item the G subgroups of a wave are added by fixed-order shuffles, then the 4 waves
+// through LDS, all in FP64.  With VJP the per-term weight is q_i (gF_i . m_l).
+struct KlParticleF64 { double sx, sy, sz, q; };
+
+template <int TILE, int G, int KPL, bool VJP>
+__global__ __launch_bounds__(256) void rho_klane_f64_kernel(WsView w, const double* __restrict__ x,
+                                                           const double* __restrict__ y,
+                                                           const double* __restrict__ z,
+                                                           const double* __restrict__ q,
+                                                           const int32_t* __restrict__ m,
+                                                           const double* __restrict__ gF, int64_t n_total,
+                                                           int32_t n_items) {
+  constexpr int KL = 64 / G;
+  constexpr int PW = TILE / 4;
+  constexpr int STEPS = (PW + G - 1) / G;
+  constexpr int PWP = STEPS * G;
+  using Pt = KlParticleF64;
+  __shared__ double2 turns[kTurnRows];
+  __shared__ __align__(16) Pt tile[4 * PWP];
+  __shared__ __align__(16) Pt tgw[VJP ? 4 * PWP : 1];   // q gF of each slot (VJP)
+  __shared__ double red[4][2 * KPL][KL];
+  build_turn_table(turns);   // the item loop's first barrier precedes every use
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int kl = lane % KL;
+  const int g = lane / KL;
+  for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const RhoItem it = w.rho_items[__builtin_amdgcn_readfirstlane(item)];
+    const SysDesc sd = w.sys[it.sys];
+    const int first = it.tile * TILE;
+    const int cnt = min(TILE, sd.n - first);
+    const double invL = 1.0 / sd.L;
+    double mx[KPL], my[KPL], mz[KPL];
+#pragma unroll
+    for (int c = 0; c < KPL; ++c) {
+      const int kk = kl + KL * c;
+      const bool ok = g < G && kk < it.nk;
+      const int64_t gk = sd.k_off + it.k0 + min(kk, max(it.nk - 1, 0));
+      const int32_t a = m[3 * gk], b = m[3 * gk + 1], d = m[3 * gk + 2];
+      mx[c] = ok ? (double)a : 0.0;
+      my[c] = ok ? (double)b : 0.0;
+      mz[c] = ok ? (double)d : 0.0;
+    }
+    __syncthreads();   // the previous item's readers of tile and red are done
+    for (int i = tid; i < 4 * PWP; i += 256) {
+      const int wv = i / PWP, sl = i % PWP;
+      const int pi = wv * PW + sl;
+      Pt v = {0.0, 0.0, 0.0, 0.0}, qg = {0.0, 0.0, 0.0, 0.0};
+      if (sl < PW && pi < cnt) {
+        const int64_t gi = sd.n_off + first + pi;
+        v.sx = table_coord(x[gi], invL);
+        v.sy = table_coord(y[gi], invL);
+        v.sz = table_coord(z[gi], invL);
+        v.q = q[gi];
+        if (VJP) qg = Pt{v.q * gF[gi], v.q * gF[n_total + gi], v.q * gF[2 * n_total + gi], 0.0};
+      }
+      tile[i] = v;
+      if (VJP) tgw[i] = qg;
+    }
+    __syncthreads();
+    double acc[2 * KPL];
+#pragma unroll
+    for (int c = 0; c < 2 * KPL; ++c) acc[c] = 0.0;
+    if (g < G) {
+      const Pt* tp = tile + wave * PWP + g;
+      const Pt* gp = tgw + (VJP ? wave * PWP + g : 0);
+      for (int j = 0; j < STEPS; ++j) {
+        const Pt v = tp[j * G];
+        Pt qg = {0.0, 0.0, 0.0, 0.0};
+        if (VJP) qg = gp[j * G];
+#pragma unroll
+        for (int c = 0; c < KPL; ++c) {
+          double sn, cs;
+          sincos_phase_tab(dot_f64(mx[c], my[c], mz[c], v.sx, v.sy, v.sz), turns, &sn, &cs);
+          double wt = v.q;
+          if (VJP) wt = fma(qg.sx, mx[c], fma(qg.sy, my[c], qg.sz * mz[c]));
+          acc[c] = fma(wt, cs, acc[c]);
+          acc[KPL + c] = fma(wt, sn, acc[KPL + c]);
+        }
+      }
+    }
+    // the G subgroups of the wave (lanes kl, kl + KL, ...) in a fixed order
+#pragma unroll
+    for (int c = 0; c < 2 * KPL; ++c) {
+      double sum = 0.0;
+#pragma unroll
+      for (int gg = 0; gg < G; ++gg) sum += __shfl(acc[c], kl + KL * gg, 64);
+      if (g == 0) red[wave][c][kl] = sum;
+    }
+    __syncthreads();
+    double* part = w.partials + 2 * sd.part_off;
+    for (int o = tid; o < 2 * it.nk; o += 256) {
+      const int kk = o >> 1, comp = o & 1;
+      const int c = kk / KL, r = kk % KL;
+      double sum = 0.0;
+#pragma unroll
+      for (int wv = 0; wv < 4; ++wv) sum += red[wv][comp * KPL + c][r];
       const int64_t kidx = it.k0 + kk;
       part[2 * (kidx * sd.ntiles + it.tile) + comp] = sum;
     }
@@ -1499,6 +1610,16 @@ void launch_rho_f64_t(const LaunchShape& s, const WsView& w, const double* x, co
                      s.n_total, s.n_rho_items);
 }
 
+// FP64 k-lane rho pass: one 256-thread block per item (rho_grid_cap counts waves, four a block)
+template <int TILE, int G, int KPL, bool VJP>
+void launch_rho_klane_f64_t(const LaunchShape& s, const WsView& w, const double* x, const double* y,
+                            const double* z, const double* q, const int32_t* m, const double* gF, hipStream_t st) {
+  int32_t blocks = s.n_rho_items;
+  if (s.rho_grid_cap > 0) blocks = std::min<int32_t>(blocks, std::max<int32_t>((s.rho_grid_cap + 3) / 4, 1));
+  hipLaunchKernelGGL((rho_klane_f64_kernel<TILE, G, KPL, VJP>), dim3((unsigned)std::max<int32_t>(blocks, 1)),
+                     dim3(256), 0, st, w, x, y, z, q, m, gF, s.n_total, s.n_rho_items);
+}
+
 // k-lane rho pass: one 256-thread block per item (rho_grid_cap counts waves, four a block)
 template <int TILE, int G, int KPL, bool VJP, bool FPH>
 void launch_rho_klane_t(const LaunchShape& s, const WsView& w, const double* x, const double* y,
@@ -1553,6 +1674,7 @@ void launch_tile_pass(const LaunchShape& s, const WsView& w, const double* x, co
   } else {
     const double* g = static_cast<const double*>(gF);
     switch (s.rv.wpb * 10000 + s.rv.npl * 100 + s.rv.kc) {
+      case 10805: launch_rho_klane_f64_t<512, 3, 5, VJP>(s, w, x, y, z, q, m, g, st); break;
       case 160404: launch_rho_f64_t<4, 4, VJP, 16>(s, w, x, y, z, q, m, g, st); break;
       case 40804: launch_rho_f64_t<8, 4, VJP, 4>(s, w, x, y, z, q, m, g, st); break;
       case 40404: launch_rho_f64_t<4, 4, VJP, 4>(s, w, x, y, z, q, m, g, st); break;

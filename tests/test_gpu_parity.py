@@ -87,20 +87,22 @@ def test_all_variants(precision):
             _check("c1 variants", s, alpha, P, 2001, precision, tiles=(rv, fv))
 
 
-# the k-lane rho layouts: the last two FP32 rho variants (5 wave vectors on each of 3 x 21
-# lanes, one (tile, k-range) item per block, at most 105 wave vectors per item; tiles of
-# 512 and 256 particles)
+# the k-lane rho layouts (5 wave vectors on each of 3 x 21 lanes, one (tile, k-range) item
+# per block, at most 105 wave vectors per item): FP32 variants 9 (512-particle tiles) and
+# 10 (256), FP64 variant 8 (512)
 KLANE = 9
 KLANE_256 = 10
+KLANE_F64 = 8
+KLANE_CASES = [("fp32_mixed", KLANE), ("fp32_mixed", KLANE_256), ("fp32", KLANE), ("fp32", KLANE_256),
+               ("fp64", KLANE_F64)]
 
 
-@pytest.mark.parametrize("precision", ["fp32_mixed", "fp32"])
-@pytest.mark.parametrize("rv", [KLANE, KLANE_256])
+@pytest.mark.parametrize("precision,rv", KLANE_CASES)
 @pytest.mark.parametrize("n,P", [(1300, 250), (511, 105), (2049, 106), (64, 3)])
 def test_klane_layout(n, P, rv, precision):
     """Several k-ranges per tile, a short last range, ragged and single tiles."""
     plan = Plan(Batch.single(n, P, 11.0, 0.35), precision=precision, device=dev())
-    assert plan.num_variants()[0] == KLANE_256 + 1
+    assert plan.rho_variant_info(rv)["waves_per_block"] == 1
     s = ri.random_charges(n, 11.0, 70 + n)
     _check(f"k-lane{rv} n={n}", s, 0.35, P, 300 + P, precision, tiles=(rv, 0))
 

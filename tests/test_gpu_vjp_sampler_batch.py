@@ -54,8 +54,8 @@ def test_vjp_vs_oracle_small(precision):
     assert er < tol and eq < tol
 
 
-@pytest.mark.parametrize("precision", ["fp32_mixed", "fp32"])
-@pytest.mark.parametrize("rv", [9, 10])
+@pytest.mark.parametrize("precision,rv", [("fp32_mixed", 9), ("fp32_mixed", 10), ("fp32", 9), ("fp32", 10),
+                                          ("fp64", 8)])
 def test_vjp_klane_variant(rv, precision):
     """With a k-lane rho layout selected, pass B1 runs in that layout."""
     s, alpha, P = ri.c1_small()
@@ -64,7 +64,8 @@ def test_vjp_klane_variant(rv, precision):
     gr_ref, gq_ref = oracle.vjp(s.x, s.y, s.z, s.q, m, w, s.L, 1.0, gF.double().cpu().numpy())
     er, eq = _grad_err(gr, gr_ref), _grad_err(gq, gq_ref)
     note(f"  dL/dr {er:.2e}  dL/dq {eq:.2e}")
-    assert er < FP32_TOL and eq < FP32_TOL
+    tol = 1e-12 if precision == "fp64" else FP32_TOL
+    assert er < tol and eq < tol
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32"])
@@ -154,7 +155,8 @@ def test_device_sampler_bit_exact():
 
 
 # rho variants: the per-wave layout, and (FP32 forms) the two k-lane layouts
-BATCH_RHO = [("fp64", 0), ("fp32_mixed", 0), ("fp32", 0), ("fp32_mixed", 9), ("fp32_mixed", 10), ("fp32", 9)]
+BATCH_RHO = [("fp64", 0), ("fp32_mixed", 0), ("fp32", 0), ("fp32_mixed", 9), ("fp32_mixed", 10), ("fp32", 9),
+             ("fp64", 8)]
 
 
 @pytest.mark.parametrize("precision,rv", BATCH_RHO)
