@@ -1,5 +1,8 @@
 """GPU parity of the forward path (rho, F, U) against the FP64 oracle.
 
+Plans use the tuned kernel variants ("auto", the configuration bench.py times) unless a
+test names its variants; test_all_variants runs every variant.
+
 FP64 form: every measure <= 1e-12.  FP32 forms (fixed-point phases "fp32_mixed" and
 FP32 phases "fp32"): every measure <= 1e-5.
 Cases: the 3,000-charge box, the paper's electrolyte and water shapes, the
@@ -23,7 +26,7 @@ pytestmark = pytest.mark.gpu
 TOL = {"fp64": FP64_TOL, "fp32_mixed": FP32_TOL, "fp32": FP32_TOL}
 
 
-def _run(s, alpha, m, w, precision, phase_mode="auto", tiles=None):
+def _run(s, alpha, m, w, precision, phase_mode="auto", tiles="auto"):
     plan = Plan(Batch.single(s.n, m.shape[0], s.L, alpha), precision=precision,
                 phase_mode=phase_mode, device=dev(), tiles=tiles)
     X = particles(s)
@@ -32,7 +35,7 @@ def _run(s, alpha, m, w, precision, phase_mode="auto", tiles=None):
     return F.double().cpu().numpy(), float(U.cpu()[0]), rho.cpu().numpy()
 
 
-def _check(name, s, alpha, P, seed, precision, phase_mode="auto", tiles=None):
+def _check(name, s, alpha, P, seed, precision, phase_mode="auto", tiles="auto"):
     m, w, S = rbe_sample_k(seed, 0, s.L, alpha, P)
     note(f"case {name} n={s.n} P={P} {precision} {phase_mode} tiles={tiles}")
     F, U, rho = _run(s, alpha, m, w, precision, phase_mode, tiles)

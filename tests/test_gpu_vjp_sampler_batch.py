@@ -24,7 +24,7 @@ from parity_util import FP32_TOL, dev, force_err, note, particles, rel, to_dev
 pytestmark = pytest.mark.gpu
 
 
-def _vjp_case(s, alpha, P, precision, seed=2005, tiles=None):
+def _vjp_case(s, alpha, P, precision, seed=2005, tiles="auto"):
     m, w, _ = rbe_sample_k(seed, 0, s.L, alpha, P)
     plan = Plan(Batch.single(s.n, P, s.L, alpha), precision=precision, device=dev(), tiles=tiles)
     X = particles(s)
