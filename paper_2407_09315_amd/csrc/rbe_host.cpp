@@ -200,6 +200,21 @@ void build_layout(rbe_plan* p) {
                      [](const Range& a, const Range& c) { return a.chunks > c.chunks; });
     for (const Range& r : ranges)
       for (int32_t t = 0; t < p->sys[r.b].ntiles; ++t) p->rho_items.push_back(RhoItem{r.b, t, r.k0, r.nk});
+    if (rv.wpb == 1) {
+      // k-lane blocks take one item each, and the dispatcher deals consecutive blocks to
+      // the eight XCDs in turn.  The partials of a wave vector lie tile after tile, four
+      // tiles to a 64-byte line, so within every aligned group of 32 items of one
+      // (system, k-range) block 32g + r takes tile 32g + 4 (r mod 8) + r / 8: the four
+      // tiles of a line are written from one XCD's L2.  Results do not depend on the order.
+      std::vector<RhoItem>& it = p->rho_items;
+      for (size_t g0 = 0; g0 + 32 <= it.size(); g0 += 32) {
+        const RhoItem& a = it[g0];
+        const RhoItem& z = it[g0 + 31];
+        if (a.sys != z.sys || a.k0 != z.k0 || z.tile != a.tile + 31) continue;
+        const RhoItem first = a;
+        for (int r = 0; r < 32; ++r) it[g0 + (size_t)r] = RhoItem{first.sys, first.tile + 4 * (r % 8) + r / 8, first.k0, first.nk};
+      }
+    }
   }
   // sampler tables: header (S, 2M+1, p, k_off) and c_-M .. c_M per system, fixed stride
   p->sampler_ok = true;
