@@ -20,8 +20,10 @@ two FLOP each.  achieved = FLOP-eq x N * P / kernel time (HIP events around
 the dominant pass's kernel on its launch stream).
 
 cpu_baseline: the FP64 oracle (plain C, OpenMP over independent outputs) on
-the same box, the same system and the same wave vectors, repeated for about
-10 s; it also gives the stated error of each GPU form.
+the same box, the same system and the same wave vectors, median of 3 full
+evaluations on all host threads and on one; it also gives the stated error of
+each GPU form (relative RMS force error and the largest per-particle error
+over the RMS force, energy and rho errors).
 """
 from __future__ import annotations
 
@@ -269,19 +271,52 @@ def traffic_from_profile(kernel: str):
         return None
 
 
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
 def cpu_baseline(s, P, res):
+    """The FP64 oracle on the host: one full evaluation (rho + F + U) of the benchmark
+    system with the GPU run's wave vectors, median of 3 timed runs after a warm-up, on all
+    the threads OpenMP gives it and on one thread.  Its result also gives each GPU form's
+    error."""
     import oracle
     m, w = res["fp32"]["m"], res["fp32"]["w"]
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        F_ref, U_ref, rho_ref = oracle.force_energy(s.x, s.y, s.z, s.q, m, w, s.L)
-        reps += 1
-        if time.perf_counter() - t0 > 10.0 or reps >= 5:
-            break
-    dt = (time.perf_counter() - t0) / reps
-    base = {"value": round(s.n * P / dt / 1e9, 5), "unit": "G(particle·k)/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "sample": f"full evaluation (rho + F + U) of the same 1M-atom system and P={P} "
-                                        f"wave vectors, {reps} repetitions, {dt:.2f} s each"}
+
+    def timed(reps):
+        ts, out = [], None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            out = oracle.force_energy(s.x, s.y, s.z, s.q, m, w, s.L)
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), out
+
+    threads = oracle.num_threads()
+    timed(1)                                    # warm-up
+    t_all, (F_ref, U_ref, rho_ref) = timed(3)
+    oracle.set_num_threads(1)
+    try:
+        t_one, _ = timed(3)
+    finally:
+        oracle.set_num_threads(threads)
+    model, ncpu, navail = cpu_info()
+    terms = s.n * P
+    base = {"value": round(terms / t_all / 1e9, 5), "unit": "G(particle·k)/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"full evaluation (rho + F + U) of the same 1M-atom system and P={P} wave vectors, "
+                      f"median of 3 runs after a warm-up: {t_all:.3f} s on {threads} threads",
+            "single_core": {"value": round(terms / t_one / 1e9, 5), "unit": "G(particle·k)/s", "cores": 1,
+                            "s_per_evaluation": round(t_one, 3), "sample": "the same evaluation, median of 3 runs"},
+            "s_per_evaluation": round(t_all, 3), "cpu_model": model, "nproc": ncpu, "cpus_available": navail}
     errs = {}
     for key, prec in (("fp32", "fp32_mixed"), ("fp64", "fp64"), ("fp32_phase", "fp32")):
         if key not in res:
@@ -293,7 +328,9 @@ def cpu_baseline(s, P, res):
             F_ref2, U_ref2, rho_ref2 = F_ref, U_ref, rho_ref
         F = r["F"]
         rc = r["rho"][:, 0] + 1j * r["rho"][:, 1]
+        dF = np.sqrt(np.sum((F - F_ref2) ** 2, axis=0))
         errs[prec] = {"force_rel_rms": float(np.sqrt(np.sum((F - F_ref2) ** 2) / np.sum(F_ref2 ** 2))),
+                      "force_max_particle_over_rms": float(dF.max() / np.sqrt(np.mean(np.sum(F_ref2 ** 2, axis=0)))),
                       "energy_rel": float(abs(r["U"] - U_ref2) / abs(U_ref2)),
                       "rho_max_over_qnorm": float(np.max(np.abs(rc - rho_ref2)) / np.sqrt(np.sum(s.q ** 2)))}
     return base, errs

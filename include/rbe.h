@@ -43,7 +43,13 @@
  * Errors.  Every call returns an rbe_status.  Arguments are checked on the
  * host before anything is enqueued; on failure nothing is launched and
  * rbe_last_error() (thread-local) holds a message.  Nothing aborts.
- * Non-finite inputs are not checked on the device and propagate as NaN.
+ * Non-finite positions or charges are not rejected; they propagate as NaN into rho
+ * and from there into every force, the energy, the virial and the VJP outputs.
+ *
+ * Wave vectors.  The sampler never draws m = (0, 0, 0), but a caller-supplied list may
+ * hold it (k = 0 is excluded from the Ewald sum): such a row gets rho_l = sum_j q_j
+ * (to the rounding of the precision) and the weight c_l = 0, so it adds nothing to F,
+ * U, the virial or the VJP, whatever its w_l.
  *
  * Determinism.  Every reduction runs in a fixed order, so results are
  * bitwise reproducible for the same inputs, plan parameters and device.
@@ -58,7 +64,7 @@
 extern "C" {
 #endif
 
-#define RBE_ABI_VERSION 1
+#define RBE_ABI_VERSION 2
 
 typedef enum {
     RBE_OK = 0,
@@ -91,6 +97,21 @@ typedef enum {
                                  pass reads them */
 } rbe_phase_mode;
 
+/*
+ * A batch of B independent periodic cubic systems (all host memory, read only by
+ * rbe_plan_create, which copies what it needs).  System b owns particles
+ * [sys_off[b], sys_off[b+1]) and wave vectors [k_off[b], k_off[b+1]) of the
+ * concatenated arrays; L[b] is its box edge (A) and alpha[b] its Ewald splitting
+ * parameter (A^-2), both finite and > 0.
+ */
+typedef struct {
+    int32_t B;                /* number of systems, > 0 */
+    const int64_t *sys_off;   /* B + 1 non-decreasing particle offsets, sys_off[0] = 0 */
+    const int64_t *k_off;     /* B + 1 non-decreasing wave-vector offsets, k_off[0] = 0 */
+    const double *L;          /* B box edges */
+    const double *alpha;      /* B splitting parameters */
+} rbe_batch_desc;
+
 typedef struct rbe_plan rbe_plan;   /* opaque; host memory owned by the library */
 typedef struct rbe_graph rbe_graph; /* opaque; an instantiated HIP graph of one evaluation */
 
@@ -122,15 +143,17 @@ rbe_status rbe_normalization(double L, double alpha, double *S_out);
 rbe_status rbe_ewald_weights(double L, double alpha, int32_t P, const int32_t *m, double *w_out);
 
 /*
- * Create a plan for B systems.  sys_off, k_off: (host) B+1 non-decreasing
- * offsets starting at 0 (particles, wave vectors).  L, alpha: (host) B values
- * each, > 0.  precision: rbe_precision; phase_mode: rbe_phase_mode.  The plan
- * copies everything it needs; the arrays may be freed afterwards.  Tile
- * parameters come from the built-in defaults or from rbe_plan_set_tiles.
+ * Create a plan for the batch `batch` (host; see rbe_batch_desc).  precision:
+ * rbe_precision; phase_mode: rbe_phase_mode.  The plan copies everything it needs;
+ * the descriptor and its arrays may be freed afterwards.  Tile parameters come from
+ * the built-in defaults or from rbe_plan_set_tiles.  RBE_EINVAL for a NULL
+ * descriptor or array, B <= 0, offsets that do not start at 0 or decrease, a
+ * system of 2^30 or more particles or wave vectors, L or alpha not finite and
+ * > 0, or an unknown enum; RBE_EUNSUPPORTED for the combinations noted at
+ * rbe_precision and rbe_phase_mode.  *out is NULL on failure.
  */
-rbe_status rbe_plan_create(int32_t B, const int64_t *sys_off, const int64_t *k_off,
-                           const double *L, const double *alpha, int32_t precision,
-                           int32_t phase_mode, rbe_plan **out);
+rbe_status rbe_plan_create(const rbe_batch_desc *batch, int32_t precision, int32_t phase_mode,
+                           rbe_plan **out);
 
 /* Bytes of device workspace the plan needs (a multiple of 256). */
 size_t rbe_plan_workspace_bytes(const rbe_plan *plan);
@@ -250,14 +273,15 @@ rbe_status rbe_kspace_virial(const rbe_plan *plan, const int32_t *m, const doubl
 /*
  * Vector-Jacobian product of (U, F) (derived from the definitions above; the
  * paper has no adjoint).  Upstream gradients: gU (dev, B FP64) on U and gF
- * (dev, 3*N_total, dtype of F) on F.  Outputs (dev, dtype of F): gr
- * (3*N_total, dL/dr) and gq (N_total, dL/dq).  rho must be the forward
+ * (dev, 3*N_total, dtype of F) on F.  Outputs (dev, FP64 in every precision): gr
+ * (3*N_total, dL/dr, three planes like F) and gq (N_total, dL/dq).  The FP32
+ * forms accumulate in FP32 and write doubles.  rho must be the forward
  * structure factor.  Phases are recomputed (no phase cache is used).
  */
 rbe_status rbe_kspace_vjp(const rbe_plan *plan, const double *x, const double *y,
                           const double *z, const double *q, const int32_t *m, const double *w,
-                          const double *rho, const double *gU, const void *gF, void *gr,
-                          void *gq, void *ws, void *stream);
+                          const double *rho, const double *gU, const void *gF, double *gr,
+                          double *gq, void *ws, void *stream);
 
 /*
  * Draw the wave vectors of every system on the device: system b uses the
@@ -277,7 +301,8 @@ rbe_status rbe_sample_k_device(const rbe_plan *plan, uint64_t seed, uint64_t str
  * occupancy clamp; keep the fastest of each with one block per work item,
  * upload the plan again and report the choice and its mean kernel times in ms
  * (any output pointer may be NULL).  Arguments as for the calls it times; rho,
- * F and U are overwritten.  Synchronises `stream`.
+ * F and U are overwritten.  Synchronises `stream`.  On failure the plan keeps the
+ * variants it had and is uploaded to ws again, so it stays usable.
  */
 rbe_status rbe_plan_tune(rbe_plan *plan, const double *x, const double *y, const double *z,
                          const double *q, const int32_t *m, const double *w, double *rho, void *F,

@@ -56,6 +56,7 @@ def _load():
         d, i64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_int32
         P = ctypes.c_void_p
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
         lib.oracle_rho.argtypes = [i64, P, P, P, P, i64, P, d, P]
         lib.oracle_force_from_rho.argtypes = [i64, P, P, P, P, i64, P, P, d, P, P, P]
         lib.oracle_force_energy.argtypes = [i64, P, P, P, P, i64, P, P, d, P, P, P]
@@ -77,6 +78,11 @@ def _ptr(a):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Run later oracle calls on n OpenMP threads (timing only; results do not change)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def rho(x, y, z, q, m, L):

@@ -52,6 +52,16 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* Thread count of later OpenMP loops (for timing on a stated number of cores; the
+   results do not depend on it). */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* k_l = 2 pi m_l / L */
 static void wave_vector(const int32_t *m, int64_t l, double L, double k[3]) {
     for (int d = 0; d < 3; ++d) k[d] = TWO_PI * (double)m[3 * l + d] / L;

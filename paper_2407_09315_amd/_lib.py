@@ -25,7 +25,7 @@ SIGNATURES = {
     "rbe_sample_k": (_ST, [_U64, _U64, _D, _D, _I32, _VP, _VP, _VP]),
     "rbe_normalization": (_ST, [_D, _D, _VP]),
     "rbe_ewald_weights": (_ST, [_D, _D, _I32, _VP, _VP]),
-    "rbe_plan_create": (_ST, [_I32, _VP, _VP, _VP, _VP, _I32, _I32, _VP]),
+    "rbe_plan_create": (_ST, [_VP, _I32, _I32, _VP]),
     "rbe_plan_workspace_bytes": (_SZ, [_VP]),
     "rbe_plan_set_tiles": (_ST, [_VP, _I32, _I32]),
     "rbe_plan_num_variants": (_ST, [_VP, _VP, _VP]),
@@ -52,6 +52,13 @@ SIGNATURES = {
     "rbe_last_error": (ctypes.c_char_p, []),
     "rbe_abi_version": (_I32, []),
 }
+
+
+
+class BatchDesc(ctypes.Structure):
+    """rbe_batch_desc: B and pointers to the host offset / box arrays."""
+    _fields_ = [("B", ctypes.c_int32), ("sys_off", _VP), ("k_off", _VP), ("L", _VP), ("alpha", _VP)]
+
 
 _lib = None
 

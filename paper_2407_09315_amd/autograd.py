@@ -30,8 +30,7 @@ class RBEKSpace(torch.autograd.Function):
             gF = torch.zeros((3, plan.n_total), dtype=plan.force_dtype, device=x.device)
         gr, gq = plan.kspace_vjp(x, y, z, q, m, w, rho, gU.to(torch.float64).contiguous(),
                                  gF.to(plan.force_dtype).contiguous())
-        gr = gr.to(torch.float64)
-        return gr[0], gr[1], gr[2], gq.to(torch.float64), None, None, None
+        return gr[0], gr[1], gr[2], gq, None, None, None
 
 
 def rbe_kspace(x, y, z, q, m, w, plan: Plan):

@@ -13,7 +13,6 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librbe.so")
-RATES = os.path.join(PKG, "valu_rates")        # VALU issue-rate microbenchmark (roofline rates)
 SOURCES = ["rbe_host.cpp", "rbe_kernels.hip"]
 ARCH = "gfx950"
 
@@ -51,9 +50,6 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)
-    cmd = [cc, *flags(), "-x", "hip", os.path.join(CSRC, "valu_rates.hip"), "-o", RATES + ".tmp"]
-    subprocess.run(cmd, check=True)
-    os.replace(RATES + ".tmp", RATES)
     return LIB
 
 

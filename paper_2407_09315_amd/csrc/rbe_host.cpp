@@ -393,10 +393,15 @@ rbe_status rbe_ewald_weights(double L, double alpha, int32_t P, const int32_t* m
   return RBE_OK;
 }
 
-rbe_status rbe_plan_create(int32_t B, const int64_t* sys_off, const int64_t* k_off, const double* L,
-                           const double* alpha, int32_t precision, int32_t phase_mode, rbe_plan** out) {
+rbe_status rbe_plan_create(const rbe_batch_desc* batch, int32_t precision, int32_t phase_mode, rbe_plan** out) {
   if (out == nullptr) return fail(RBE_EINVAL, "out is NULL");
   *out = nullptr;
+  if (batch == nullptr) return fail(RBE_EINVAL, "batch descriptor is NULL");
+  const int32_t B = batch->B;
+  const int64_t* sys_off = batch->sys_off;
+  const int64_t* k_off = batch->k_off;
+  const double* L = batch->L;
+  const double* alpha = batch->alpha;
   if (B <= 0) return fail(RBE_EINVAL, "B must be > 0 (got %d)", B);
   if (!sys_off || !k_off || !L || !alpha) return fail(RBE_EINVAL, "NULL batch array");
   if (precision != RBE_FP64 && precision != RBE_FP32_MIXED && precision != RBE_FP32)
@@ -574,7 +579,7 @@ rbe_status rbe_kspace_virial(const rbe_plan* p, const int32_t* m, const double* 
 
 rbe_status rbe_kspace_vjp(const rbe_plan* p, const double* x, const double* y, const double* z,
                           const double* q, const int32_t* m, const double* w, const double* rho,
-                          const double* gU, const void* gF, void* gr, void* gq, void* ws, void* stream) {
+                          const double* gU, const void* gF, double* gr, double* gq, void* ws, void* stream) {
   rbe_status st = check_common(p, ws);
   if (st != RBE_OK) return st;
   const int64_t n = p->n_total(), P = p->p_total();
@@ -624,6 +629,8 @@ rbe_status rbe_plan_tune(rbe_plan* p, const double* x, const double* y, const do
     return r;
   };
   const int nr = p->precision == RBE_FP64 ? kNumRhoVariantsF64 : kNumRhoVariantsF32;
+  const int orig_r = p->rho_variant, orig_f = p->force_variant;
+  const int32_t orig_clamp = p->rho_clamp, orig_cap = p->rho_grid_cap;
   int best_r = p->rho_variant, best_f = p->force_variant;
   float best_rms = 1e30f, best_fms = 1e30f;
   rbe_status r = RBE_OK;
@@ -649,12 +656,24 @@ rbe_status rbe_plan_tune(rbe_plan* p, const double* x, const double* y, const do
     if (r == RBE_OK && b < best_fms) { best_fms = b; best_f = v; }
   }
   p->force_variant = best_f;
-  build_layout(p);
   for (int i = 0; i < 4; ++i) {
     (void)hipEventDestroy(ev[i]);
     p->ev[i] = saved[i];
   }
-  if (r != RBE_OK) return r;
+  if (r != RBE_OK) {
+    // keep the plan and the workspace consistent: back to the variants the call started
+    // with, uploaded again (the workspace holds the tables of the last variant timed)
+    const std::string why = g_last_error;
+    p->rho_variant = orig_r;
+    p->force_variant = orig_f;
+    p->rho_clamp = orig_clamp;
+    p->rho_grid_cap = orig_cap;
+    build_layout(p);
+    (void)rbe_plan_upload(p, ws, stream);
+    g_last_error = why;
+    return r;
+  }
+  build_layout(p);
   r = rbe_plan_upload(p, ws, stream);
   if (r != RBE_OK) return r;
   if (rho_variant) *rho_variant = best_r;

@@ -131,7 +131,7 @@ hipError_t launch_force(const LaunchShape& s, const WsView& w, const double* x, 
                         hipStream_t st);
 hipError_t launch_vjp(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                       const double* z, const double* q, const int32_t* m, const double* wk,
-                      const double* rho, const double* gU, const void* gF, void* gr, void* gq,
+                      const double* rho, const double* gU, const void* gF, double* gr, double* gq,
                       hipStream_t st);
 hipError_t launch_sample(const LaunchShape& s, const WsView& w, uint64_t seed, uint64_t stream_id,
                          const uint64_t* counter, int32_t* m, double* wk, hipStream_t st);

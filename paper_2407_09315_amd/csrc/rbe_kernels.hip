@@ -63,6 +63,14 @@ __device__ inline uint32_t fixed_fraction(double x, double invL) {
   return (uint32_t)r;
 }
 
+// q, or NaN when a coordinate is NaN or infinite (x * 0 is 0 for finite x and NaN
+// otherwise).  The fixed-point fraction of a non-finite coordinate is a finite number, so
+// the FP32-mixed passes carry the charge of such a particle as NaN instead: rho, and with
+// it every force and the energy, come out NaN.
+__device__ inline double finite_or_nan(double q, double x, double y, double z) {
+  return q + (x * 0.0 + y * 0.0 + z * 0.0);
+}
+
 // Top 23 bits of a phase (turns * 2^32) as the float 1 + t/2^32 in [1, 2): revolutions.
 __device__ inline float turns_arg(uint32_t t) {
   return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, t, 9u));
@@ -430,10 +438,11 @@ __global__ __launch_bounds__(64 * WPB) void rho_f32_kernel(WsView w, const doubl
         const int li = j * 64 + lane;
         if (li < cnt) {
           const int64_t gi = sd.n_off + first + li;
-          ux[j] = Ph::coord(x[gi], invL);
-          uy[j] = Ph::coord(y[gi], invL);
-          uz[j] = Ph::coord(z[gi], invL);
-          qv[j] = (float)q[gi];
+          const double px = x[gi], py = y[gi], pz = z[gi];
+          ux[j] = Ph::coord(px, invL);
+          uy[j] = Ph::coord(py, invL);
+          uz[j] = Ph::coord(pz, invL);
+          qv[j] = (float)finite_or_nan(q[gi], px, py, pz);
           if (VJP) {
             qgx[j] = qv[j] * gF[gi];
             qgy[j] = qv[j] * gF[n_total + gi];
@@ -594,10 +603,11 @@ __global__ __launch_bounds__(256) void rho_klane_kernel(WsView w, const double* 
       float4 qg = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if (sl < PW && pi < cnt) {
         const int64_t gi = sd.n_off + first + pi;
-        v.ux = Ph::coord(x[gi], invL);
-        v.uy = Ph::coord(y[gi], invL);
-        v.uz = Ph::coord(z[gi], invL);
-        v.q = (float)q[gi];
+        const double px = x[gi], py = y[gi], pz = z[gi];
+        v.ux = Ph::coord(px, invL);
+        v.uy = Ph::coord(py, invL);
+        v.uz = Ph::coord(pz, invL);
+        v.q = (float)finite_or_nan(q[gi], px, py, pz);
         if (VJP) qg = make_float4(v.q * gF[gi], v.q * gF[n_total + gi], v.q * gF[2 * n_total + gi], 0.0f);
       } else {
         v.ux = v.uy = v.uz = 0;
@@ -1053,6 +1063,7 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
   float fx[NPLF], fy[NPLF], fz[NPLF];
   int li[NPLF];
   double cx[NPLF], cy[NPLF], cz[NPLF];   // the particles as loaded
+  float bad[NPLF];                        // 0, or NaN for a non-finite position
 #pragma unroll
   for (int j = 0; j < NPLF; ++j) {
     li[j] = it.p0 + j * kForceBlock + tid;
@@ -1083,6 +1094,7 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
     } else {
       ux[j] = uy[j] = uz[j] = 0;
     }
+    bad[j] = (float)finite_or_nan(0.0, cx[j], cy[j], cz[j]);
   }
   for (int t0 = 0; t0 < sd.p; t0 += kTabChunk) {
     const int cnt = min(kTabChunk, sd.p - t0);
@@ -1145,7 +1157,7 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
   for (int j = 0; j < NPLF; ++j) {
     if (j * kForceBlock + tid < it.np) {
       const int64_t gi = sd.n_off + li[j];
-      const double s = -q[gi] * kscale;
+      const double s = -(q[gi] + bad[j]) * kscale;
       F[gi] = (float)(s * fx[j]);
       F[n_total + gi] = (float)(s * fy[j]);
       F[2 * n_total + gi] = (float)(s * fz[j]);
@@ -1304,7 +1316,7 @@ __global__ __launch_bounds__(kForceBlock) void vjp_b2_f32_kernel(
     WsView w, int64_t n_total, const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const double* __restrict__ q, const int32_t* __restrict__ m,
     const double* __restrict__ wk, const double* __restrict__ rho, const double* __restrict__ gU,
-    const float* __restrict__ gF, float* __restrict__ gr, float* __restrict__ gq, double rot_c,
+    const float* __restrict__ gF, double* __restrict__ gr, double* __restrict__ gq, double rot_c,
     double rot_s, int32_t n_items) {
   __shared__ TabAdjF32 tab[kTabChunk];
 for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
@@ -1378,9 +1390,9 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
     if (j * kForceBlock + tid < it.np) {
       const int64_t gi = sd.n_off + it.p0 + j * kForceBlock + tid;
       const double s = q[gi] * kscale;
-      gr[gi] = (float)(s * rx[j]);
-      gr[n_total + gi] = (float)(s * ry[j]);
-      gr[2 * n_total + gi] = (float)(s * rz[j]);
+      gr[gi] = s * rx[j];
+      gr[n_total + gi] = s * ry[j];
+      gr[2 * n_total + gi] = s * rz[j];
       gq[gi] = rq[j];
     }
   }
@@ -1791,7 +1803,7 @@ hipError_t launch_force(const LaunchShape& s, const WsView& w, const double* x, 
 
 hipError_t launch_vjp(const LaunchShape& s, const WsView& w, const double* x, const double* y,
                       const double* z, const double* q, const int32_t* m, const double* wk,
-                      const double* rho, const double* gU, const void* gF, void* gr, void* gq,
+                      const double* rho, const double* gU, const void* gF, double* gr, double* gq,
                       hipStream_t st) {
   double rc, rs;
   truncation_rotation(s.precision, &rc, &rs);
@@ -1811,8 +1823,8 @@ hipError_t launch_vjp(const LaunchShape& s, const WsView& w, const double* x, co
   const int32_t ni = s.n_force_items;
   if (s.precision == RBE_FP32_MIXED || s.precision == RBE_FP32) {
     const float* g = static_cast<const float*>(gF);
-    float* r = static_cast<float*>(gr);
-    float* qq = static_cast<float*>(gq);
+    double* r = gr;
+    double* qq = gq;
     const bool fph = s.precision == RBE_FP32;
     switch (s.fv.nplf * 2 + (fph ? 1 : 0)) {
       case 2: hipLaunchKernelGGL((vjp_b2_f32_kernel<1, false>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, rc, rs, ni); break;
@@ -1824,8 +1836,8 @@ hipError_t launch_vjp(const LaunchShape& s, const WsView& w, const double* x, co
     }
   } else {
     const double* g = static_cast<const double*>(gF);
-    double* r = static_cast<double*>(gr);
-    double* qq = static_cast<double*>(gq);
+    double* r = gr;
+    double* qq = gq;
     switch (s.fv.nplf) {
       case 1: hipLaunchKernelGGL((vjp_b2_f64_kernel<1>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, ni); break;
       case 2: hipLaunchKernelGGL((vjp_b2_f64_kernel<2>), grid, block, 0, st, w, s.n_total, x, y, z, q, m, wk, rho, gU, g, r, qq, ni); break;

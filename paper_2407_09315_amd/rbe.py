@@ -6,7 +6,9 @@ Functions with the C names take torch tensors (device memory) or numpy arrays
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -17,6 +19,25 @@ from ._lib import (RBE_FP32, RBE_FP32_MIXED, RBE_FP64, RBE_PHASE_AUTO, RBE_PHASE
                    RBE_PHASE_RECOMPUTE, RBEError, check, load)
 
 PRECISIONS = {"fp64": RBE_FP64, "fp32_mixed": RBE_FP32_MIXED, "fp32": RBE_FP32}
+
+# Library handles still alive.  At interpreter exit they are released by an atexit hook
+# (graphs first, then plans), which runs before the HIP runtime unloads; finalisers that
+# run later find the handles already released and do nothing.
+_live_graphs: "weakref.WeakSet" = weakref.WeakSet()
+_live_plans: "weakref.WeakSet" = weakref.WeakSet()
+_released_all = False
+
+
+def _release_all():
+    global _released_all
+    for g in list(_live_graphs):
+        g.close()
+    for p in list(_live_plans):
+        p.close()
+    _released_all = True
+
+
+atexit.register(_release_all)
 PHASE_MODES = {"auto": RBE_PHASE_AUTO, "recompute": RBE_PHASE_RECOMPUTE, "cached": RBE_PHASE_CACHED}
 
 
@@ -151,11 +172,16 @@ class Plan:
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.n_total = int(batch.sys_off[-1])
         self.p_total = int(batch.k_off[-1])
-        self._arrays = [np.ascontiguousarray(a) for a in (batch.sys_off, batch.k_off, batch.L, batch.alpha)]
+        self._arrays = [np.ascontiguousarray(a, dtype=t) for a, t in
+                        ((batch.sys_off, np.int64), (batch.k_off, np.int64), (batch.L, np.float64),
+                         (batch.alpha, np.float64))]
+        desc = _lib.BatchDesc(batch.B, *[_ptr(a) for a in self._arrays])
         handle = ctypes.c_void_p()
-        check(self.lib.rbe_plan_create(batch.B, *[_ptr(a) for a in self._arrays], PRECISIONS[precision],
-                                       PHASE_MODES[phase_mode], ctypes.byref(handle)), "rbe_plan_create")
+        check(self.lib.rbe_plan_create(ctypes.byref(desc), PRECISIONS[precision], PHASE_MODES[phase_mode],
+                                       ctypes.byref(handle)), "rbe_plan_create")
         self.handle = handle
+        self._events = ()
+        _live_plans.add(self)
         if isinstance(tiles, str) and tiles == "auto":
             from .tune import lookup
             tiles = lookup(precision, phase_mode, batch.B, self.n_total, self.p_total)
@@ -227,11 +253,22 @@ class Plan:
     def force_dtype(self):
         return torch.float64 if self.precision == "fp64" else torch.float32
 
-    def __del__(self):
+    def close(self):
+        """Release the plan (host memory) and drop the workspace; the plan is unusable afterwards."""
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and not _released_all:
             self.lib.rbe_plan_destroy(h)
-            self.handle = None
+        self.handle = None
+        self._events = ()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        self.close()
 
     # -- device calls (inputs: float64 x, y, z, q; int32 m (P_total, 3); float64 w)
     def _check_particles(self, x, y, z, q):
@@ -288,17 +325,21 @@ class Plan:
         _dev(gU, torch.float64, "gU")
         _dev(gF, self.force_dtype, "gF")
         if gr is None:
-            gr = torch.empty((3, self.n_total), dtype=self.force_dtype, device=self.device)
+            gr = torch.empty((3, self.n_total), dtype=torch.float64, device=self.device)
         if gq is None:
-            gq = torch.empty(self.n_total, dtype=self.force_dtype, device=self.device)
+            gq = torch.empty(self.n_total, dtype=torch.float64, device=self.device)
+        _dev(gr, torch.float64, "gr")
+        _dev(gq, torch.float64, "gq")
         rbe_kspace_vjp(self.handle, x, y, z, q, m, w, rho, gU, gF, gr, gq, self.ws, stream)
         return gr, gq
 
     def set_timing_events(self, rho_begin=None, rho_end=None, force_begin=None, force_end=None):
         """Record torch.cuda.Events (already recorded once, so their handles exist) around the kernels."""
-        h = [ctypes.c_void_p(e.cuda_event) if e is not None else ctypes.c_void_p(0)
-             for e in (rho_begin, rho_end, force_begin, force_end)]
+        evs = (rho_begin, rho_end, force_begin, force_end)
+        h = [ctypes.c_void_p(e.cuda_event) if e is not None else ctypes.c_void_p(0) for e in evs]
         check(self.lib.rbe_plan_set_timing_events(self.handle, *h), "rbe_plan_set_timing_events")
+        # the plan records into these events on later calls: keep them alive while set
+        self._events = tuple(e for e in evs if e is not None)
 
     def set_grid_caps(self, rho_cap: int, force_cap: int):
         check(self.lib.rbe_plan_set_grid_caps(self.handle, rho_cap, force_cap), "rbe_plan_set_grid_caps")
@@ -364,12 +405,26 @@ class EvalGraph:
                                         _ptr(self.F), _ptr(self.U), _ptr(plan.ws), ctypes.byref(handle)),
               "rbe_graph_create")
         self.handle = handle
+        _live_graphs.add(self)
 
     def launch(self, stream=None):
+        if self.handle is None:
+            raise RuntimeError("the graph was closed")
         check(self.plan.lib.rbe_graph_launch(self.handle, _stream(stream)), "rbe_graph_launch")
 
-    def __del__(self):
+    def close(self):
+        """Destroy the HIP graph; waits for the device first, since a replay may still run."""
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and not _released_all:
+            torch.cuda.synchronize(self.plan.device)
             self.plan.lib.rbe_graph_destroy(h)
-            self.handle = None
+        self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        self.close()

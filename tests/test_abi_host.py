@@ -34,7 +34,46 @@ def test_library_exports_every_declared_symbol():
     for name in names:
         assert hasattr(lib, name), name
         assert name in _lib.SIGNATURES, f"binding lacks {name}"
-    assert lib.rbe_abi_version() == 1
+    assert lib.rbe_abi_version() == 2
+
+
+_CTYPE_OF = {"int32_t": ctypes.c_int32, "uint64_t": ctypes.c_uint64, "double": ctypes.c_double,
+             "size_t": ctypes.c_size_t, "rbe_status": ctypes.c_int}
+
+
+def _prototypes():
+    """name -> (return C type, [parameter C types]) of every function rbe.h declares."""
+    src = open(os.path.join(ROOT, "include", "rbe.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for ret, name, params in re.findall(r"([A-Za-z_][\w \*]*?)\b(rbe_[a-z0-9_]+)\s*\(([^)]*)\)\s*;", src):
+        ps = [p.strip() for p in params.split(",") if p.strip() and p.strip() != "void"]
+        out[name] = (ret.strip(), ps)
+    return out
+
+
+def _ctype(decl: str, is_return: bool = False):
+    if "*" in decl:
+        return ctypes.c_char_p if (is_return and "char" in decl) else ctypes.c_void_p
+    base = decl.replace("const", "").split()[0]
+    if base == "void":
+        return None
+    return _CTYPE_OF[base]
+
+
+def test_binding_signatures_match_header():
+    """Every ctypes signature of the binding has the header's parameter count and kinds."""
+    protos = _prototypes()
+    assert set(protos) == set(_lib.SIGNATURES), set(protos) ^ set(_lib.SIGNATURES)
+    for name, (ret, params) in protos.items():
+        res, args = _lib.SIGNATURES[name]
+        assert _ctype(ret, True) == res, (name, ret, res)
+        assert len(args) == len(params), (name, params, args)
+        for p, a in zip(params, args):
+            assert _ctype(p) == a, (name, p, a)
+    # the VJP writes FP64 gradients in every precision
+    assert protos["rbe_kspace_vjp"][1][10].startswith("double") and protos["rbe_kspace_vjp"][1][11].startswith("double")
+    assert protos["rbe_plan_create"][1][0].startswith("const rbe_batch_desc")
 
 
 @pytest.mark.parametrize("seed,stream,L,alpha,P", [
@@ -66,7 +105,10 @@ def _create(B, so, ko, L, a, prec=0, mode=0):
     h = ctypes.c_void_p()
     arrs = [np.ascontiguousarray(v) for v in (np.asarray(so, np.int64), np.asarray(ko, np.int64),
                                               np.asarray(L, np.float64), np.asarray(a, np.float64))]
-    st = lib.rbe_plan_create(B, *[rbe._ptr(v) for v in arrs], prec, mode, ctypes.byref(h))
+    desc = _lib.BatchDesc(B, *[rbe._ptr(v) for v in arrs])
+    st = lib.rbe_plan_create(ctypes.byref(desc), prec, mode, ctypes.byref(h))
+    if st != 0:
+        assert not h.value   # *out is NULL on failure
     return st, h
 
 
@@ -89,6 +131,10 @@ def test_plan_validation():
         assert st == _lib.RBE_EINVAL, args
     st, _ = _create(1, [0, 10], [0, 5], [3.0], [1.0], prec=7)
     assert st == _lib.RBE_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.rbe_plan_create(None, 0, 0, ctypes.byref(h)) == _lib.RBE_EINVAL and not h.value
+    null_arrays = _lib.BatchDesc(1, None, None, None, None)
+    assert lib.rbe_plan_create(ctypes.byref(null_arrays), 0, 0, ctypes.byref(h)) == _lib.RBE_EINVAL
     st, _ = _create(1, [0, 10], [0, 5], [3.0], [1.0], prec=0, mode=2)
     assert st == _lib.RBE_EUNSUPPORTED
     # the phase cache exists for the fixed-point FP32 phases only

@@ -203,3 +203,34 @@ def test_rbe_mean_converges_to_full_ewald(oracle_lib):
     assert np.max(np.abs(z)) < 7
     zU = (Us.mean() - Uref) / (Us.std(ddof=1) / math.sqrt(B))
     assert abs(zU) < 4
+
+
+@pytest.mark.parametrize("what", ["nan_x", "inf_y", "nan_q"])
+def test_non_finite_input_gives_nan(oracle_lib, what):
+    """The contract the library follows: a non-finite position or charge makes rho, every
+    force and the energy NaN (the definition evaluated literally)."""
+    s = ri.uniform_pm1(40, 6.0, 5)
+    if what == "nan_x":
+        s.x[7] = np.nan
+    elif what == "inf_y":
+        s.y[7] = np.inf
+    else:
+        s.q[7] = np.nan
+    m, _ = sampler.sample_k(3, 0, s.L, 0.5, 6)
+    w = np.full(6, sampler.normalization_S(s.L, 0.5) / 6)
+    F, U, rho = oracle_lib.force_energy(s.x, s.y, s.z, s.q, m, w, s.L)
+    assert np.all(np.isnan(rho)) and np.isnan(U) and np.all(np.isnan(F))
+
+
+def test_thread_count_does_not_change_results(oracle_lib):
+    s = ri.uniform_pm1(500, 8.0, 6)
+    m, _ = sampler.sample_k(4, 0, s.L, 0.4, 12)
+    w = np.ones(12)
+    a = oracle_lib.force_energy(s.x, s.y, s.z, s.q, m, w, s.L)
+    n0 = oracle_lib.num_threads()
+    oracle_lib.set_num_threads(1)
+    try:
+        b = oracle_lib.force_energy(s.x, s.y, s.z, s.q, m, w, s.L)
+    finally:
+        oracle_lib.set_num_threads(n0)
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1] and np.array_equal(a[2], b[2])
