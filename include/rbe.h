@@ -341,6 +341,29 @@ rbe_status rbe_graph_create(const rbe_plan *plan, uint64_t seed, uint64_t stream
 rbe_status rbe_graph_launch(const rbe_graph *graph, void *stream);
 void rbe_graph_destroy(rbe_graph *graph);
 
+/*
+ * rbe_evaluate without a workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same kernels and results as rbe_evaluate (bitwise), with the
+ * workspace replaced by a library-owned device scratch array of 64 MiB, one per
+ * device, alive until the process ends.  The call allocates nothing and frees
+ * nothing; the caller still passes every input and output.
+ *   Limit: the plan's current layout must fit the scratch; a larger one (about
+ *   10M charges at P = 200, or the phase cache of all but small systems) returns
+ *   RBE_EWORKSPACE before anything is enqueued -- use rbe_evaluate then.
+ *   Sharing: all calls on one device share its scratch.  The first call with a
+ *   plan (or after rbe_plan_set_tiles / rbe_plan_tune changed its layout, or after
+ *   another plan used the scratch) enqueues an upload of the plan's tables ahead
+ *   of the kernels.  Calls that may overlap on one device -- concurrent host
+ *   threads, or different streams without synchronisation between them -- race on
+ *   the scratch and must be serialised by the caller.
+ *   Errors: as rbe_evaluate; RBE_EUNSUPPORTED for device ordinals >= 64.
+ */
+rbe_status rbe_evaluate_static(const rbe_plan *plan, uint64_t seed, uint64_t stream_base,
+                               uint64_t *step_counter, const double *x, const double *y,
+                               const double *z, const double *q, int32_t *m, double *w,
+                               double *rho, void *F, double *U, void *stream);
+
 /* ---------------------------------------------------------------- diagnostics */
 
 const char *rbe_status_string(rbe_status status);

@@ -45,6 +45,7 @@ SIGNATURES = {
     "rbe_plan_set_timing_events": (_ST, [_VP] * 5),
     "rbe_evaluate": (_ST, [_VP, _U64, _U64] + [_VP] * 12),
     "rbe_kspace_virial": (_ST, [_VP] * 7),
+    "rbe_evaluate_static": (_ST, [_VP, _U64, _U64] + [_VP] * 11),
     "rbe_graph_create": (_ST, [_VP, _U64, _U64] + [_VP] * 12),
     "rbe_graph_launch": (_ST, [_VP, _VP]),
     "rbe_graph_destroy": (None, [_VP]),

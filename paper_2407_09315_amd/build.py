@@ -38,8 +38,9 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
         cmd = [cc, *flags(), "-c", os.path.join(CSRC, src), "-o", obj]
-        if src.endswith(".hip"):
-            cmd[1:1] = ["-x", "hip"]
+        # both sources are HIP: rbe_host.cpp also defines a device array (the scratch of
+        # rbe_evaluate_static)
+        cmd[1:1] = ["-x", "hip"]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -123,6 +124,7 @@ struct rbe_plan {
   size_t ws_bytes = 0;      // workspace size: the largest layout over all variants
   int64_t n_partials = 0;   // complex slots
   int64_t n_cache = 0;      // (cos, sin) pairs
+  uint64_t layout_id = 0;   // unique per built layout (process-wide), see rbe_evaluate_static
 
   int64_t n_total() const { return sys_off[B]; }
   int64_t p_total() const { return k_off[B]; }
@@ -265,6 +267,8 @@ void build_layout(rbe_plan* p) {
   p->off_cache = o; o = align_up(o + 2 * sizeof(float) * (size_t)p->n_cache);
   p->off_frows = o; o = align_up(o + sizeof(ForceRowF32) * (size_t)p->p_total());
   p->total = std::max<size_t>(o, kAlign);
+  static std::atomic<uint64_t> next_layout_id{0};
+  p->layout_id = ++next_layout_id;
 }
 
 WsView view_of(const rbe_plan* p, void* ws) {
@@ -323,6 +327,26 @@ rbe_status check_common(const rbe_plan* p, const void* ws) {
 }
 
 bool need(const void* ptr, int64_t count) { return count == 0 || ptr != nullptr; }
+
+// Copies of the plan's host tables (system rows, work lists, reduction descriptors,
+// sampler tables) into ws, enqueued on s.  The source is pageable host memory owned by
+// the plan, so each copy has read it by the time hipMemcpyAsync returns.
+rbe_status enqueue_upload(const rbe_plan* p, void* ws, hipStream_t s) {
+  char* b = static_cast<char*>(ws);
+  struct Copy { size_t off; const void* src; size_t bytes; } copies[] = {
+      {p->off_sys, p->sys.data(), sizeof(SysDesc) * p->sys.size()},
+      {p->off_rho, p->rho_items.data(), sizeof(RhoItem) * p->rho_items.size()},
+      {p->off_force, p->force_items.data(), sizeof(ForceItem) * p->force_items.size()},
+      {p->off_kred, p->kred.data(), sizeof(KRed) * p->kred.size()},
+      {p->off_cdf, p->cdf.data(), sizeof(double) * p->cdf.size()},
+  };
+  for (const Copy& c : copies) {
+    if (c.bytes == 0) continue;
+    hipError_t e = hipMemcpyAsync(b + c.off, c.src, c.bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(plan upload)");
+  }
+  return RBE_OK;
+}
 
 }  // namespace
 
@@ -518,19 +542,8 @@ rbe_status rbe_plan_upload(const rbe_plan* p, void* ws, void* stream) {
   rbe_status st = check_common(p, ws);
   if (st != RBE_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  char* b = static_cast<char*>(ws);
-  struct Copy { size_t off; const void* src; size_t bytes; } copies[] = {
-      {p->off_sys, p->sys.data(), sizeof(SysDesc) * p->sys.size()},
-      {p->off_rho, p->rho_items.data(), sizeof(RhoItem) * p->rho_items.size()},
-      {p->off_force, p->force_items.data(), sizeof(ForceItem) * p->force_items.size()},
-      {p->off_kred, p->kred.data(), sizeof(KRed) * p->kred.size()},
-      {p->off_cdf, p->cdf.data(), sizeof(double) * p->cdf.size()},
-  };
-  for (const Copy& c : copies) {
-    if (c.bytes == 0) continue;
-    hipError_t e = hipMemcpyAsync(b + c.off, c.src, c.bytes, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(plan upload)");
-  }
+  st = enqueue_upload(p, ws, s);
+  if (st != RBE_OK) return st;
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(plan upload)");
   return RBE_OK;
@@ -730,6 +743,26 @@ hipError_t enqueue_evaluation(const rbe_plan* p, uint64_t seed, uint64_t stream_
   return e;
 }
 
+// ---------------------------------------------------------------- evaluation without allocation
+
+// Device scratch of rbe_evaluate_static: the plan tables, tile partial sums and force rows
+// that rbe_evaluate keeps in the caller's workspace.  Every device the library runs on
+// holds its own copy from the time the code object is loaded until the process ends.
+// In host code `scratch` names a host-side stand-in, never the device memory: the device
+// address comes from hipGetSymbolAddress, once per device, and only that address is used.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+// Per device: the address of its scratch (null until looked up) and the layout whose
+// tables were last uploaded into it (0: none).
+struct StaticScratch {
+  void* ptr = nullptr;
+  uint64_t layout_id = 0;
+};
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_static_mu;
+StaticScratch g_static[kMaxStaticDevices];
+
 }  // namespace
 
 rbe_status rbe_evaluate(const rbe_plan* p, uint64_t seed, uint64_t stream_base, uint64_t* step_counter,
@@ -786,6 +819,55 @@ void rbe_graph_destroy(rbe_graph* g) {
   (void)hipGraphExecDestroy(g->exec);
   (void)hipGraphDestroy(g->graph);
   delete g;
+}
+
+rbe_status rbe_evaluate_static(const rbe_plan* p, uint64_t seed, uint64_t stream_base, uint64_t* step_counter,
+                               const double* x, const double* y, const double* z, const double* q, int32_t* m,
+                               double* w, double* rho, void* F, double* U, void* stream) {
+  if (p == nullptr) return fail(RBE_EINVAL, "plan is NULL");
+  if (p->total > kStaticScratchBytes)
+    return fail(RBE_EWORKSPACE,
+                "the plan needs %zu bytes of scratch, more than the %zu bytes rbe_evaluate_static holds "
+                "(use rbe_evaluate with a workspace)",
+                p->total, kStaticScratchBytes);
+  rbe_status st = device_ok();
+  if (st != RBE_OK) return st;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxStaticDevices)
+    return fail(RBE_EUNSUPPORTED, "device %d is beyond the %d devices rbe_evaluate_static serves", dev,
+                kMaxStaticDevices);
+  void* ws = nullptr;
+  bool upload = false;
+  {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticScratch& slot = g_static[dev];
+    if (slot.ptr == nullptr) {
+      // first call on this device, which is current: the device address of its copy
+      void* ptr = nullptr;
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+      if (ptr == nullptr) return fail(RBE_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+      slot.ptr = ptr;
+    }
+    ws = slot.ptr;
+    upload = slot.layout_id != p->layout_id;
+  }
+  st = check_evaluation(p, x, y, z, q, m, w, rho, F, U, ws);
+  if (st != RBE_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (upload) {
+    st = enqueue_upload(p, ws, s);
+    if (st != RBE_OK) return st;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static[dev].layout_id = p->layout_id;
+  }
+  // every scratch region the evaluation reads (partials, force rows) is written earlier in
+  // the same evaluation, so nothing needs clearing between calls
+  e = enqueue_evaluation(p, seed, stream_base, step_counter, x, y, z, q, m, w, rho, F, U, ws, s);
+  if (e != hipSuccess) return hip_fail(e, "rbe_evaluate_static launch");
+  return RBE_OK;
 }
 
 rbe_status rbe_sample_k_device(const rbe_plan* p, uint64_t seed, uint64_t stream_id, int32_t* m, double* w,

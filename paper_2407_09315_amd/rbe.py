@@ -115,6 +115,12 @@ def rbe_evaluate(plan, seed, stream_base, step_counter, x, y, z, q, m, w, rho, F
           "rbe_evaluate")
 
 
+def rbe_evaluate_static(plan, seed, stream_base, step_counter, x, y, z, q, m, w, rho, F, U, stream=None):
+    check(load().rbe_evaluate_static(plan, seed, stream_base, _ptr(step_counter), _ptr(x), _ptr(y), _ptr(z),
+                                     _ptr(q), _ptr(m), _ptr(w), _ptr(rho), _ptr(F), _ptr(U), _stream(stream)),
+          "rbe_evaluate_static")
+
+
 def rbe_kspace_virial(plan, m, w, rho, W, ws, stream=None):
     check(load().rbe_kspace_virial(plan, _ptr(m), _ptr(w), _ptr(rho), _ptr(W), _ptr(ws), _stream(stream)),
           "rbe_kspace_virial")
