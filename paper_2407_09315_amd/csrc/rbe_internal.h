@@ -32,16 +32,23 @@ struct KRed {
   int32_t sys;
 };
 
-// Force-pass row of one wave vector in the FP32 forms (32 bytes): m_l, its float copy, and
-// c_l times the structure factor rotated onto the form's phases.  Written once per
-// evaluation; every force block copies its system's rows into LDS.
+// Force-pass row of one wave vector in the FP32 forms (64 bytes, four 16-byte quarters),
+// written once per evaluation from the reduced rho; every force block copies the two
+// quarters its form reads into LDS.  With rho'_l = C'_l + i S'_l the structure factor rotated
+// onto the form's phases, R_l = c_l |rho'_l| and delta_l = 1/4 - arg(rho'_l) / (2 pi) turns,
+//   c_l (S'_l cos theta - C'_l sin theta) = R_l cos(theta + 2 pi delta_l),
+// so a recomputed term needs one cosine of the phase shifted by delta_l.
 struct ForceRowF32 {
-  int32_t mx, my, mz;
-  float a;              // c_l * S'_l
-  float fx, fy, fz;     // m_l as float
-  float b;              // c_l * C'_l
+  uint32_t d;           // quarter 0: delta_l as a 32-bit fixed-point fraction of a turn and
+  int32_t mx, my, mz;   //   m_l; quarter 1: R_l m_l (fixed-point phases, 28 bytes read)
+  float gx, gy, gz;
+  float pad0;
+  float fx, fy, fz;     // quarter 2: m_l as float, delta_l in turns in [0, 1); quarter 3: R_l m_l
+  float dt;             //   and R_l (FP32 phases; the phase-cache pass forms c_l S'_l and
+  float hx, hy, hz;     //   c_l C'_l from them)
+  float r;
 };
-static_assert(sizeof(ForceRowF32) == 32, "ForceRowF32 layout");
+static_assert(sizeof(ForceRowF32) == 64, "ForceRowF32 layout");
 
 // Sampler table of system b: cdf[b * stride ...] = S, 2M+1, p, k_off (as doubles), then the
 // 2M+1 prefix sums (zero-padded to the stride), so a table's address needs no other lookup.

@@ -88,6 +88,15 @@ __device__ inline uint64_t phase_u64(int32_t mx, int32_t my, int32_t mz, uint32_
   t = (uint64_t)(uint32_t)my * uy + t;
   return (uint64_t)(uint32_t)mx * ux + t;
 }
+// m.u + d mod 2^32, a phase shifted by the fixed-point offset in the low word of d (the high
+// word may hold anything: it does not reach the low 32 bits of the sum).  d is the first
+// addend, so the shift costs no instruction.
+__device__ inline uint64_t phase_u64_off(int32_t mx, int32_t my, int32_t mz, uint32_t ux, uint32_t uy, uint32_t uz,
+                                         uint64_t d) {
+  uint64_t t = (uint64_t)(uint32_t)mz * uz + d;
+  t = (uint64_t)(uint32_t)my * uy + t;
+  return (uint64_t)(uint32_t)mx * ux + t;
+}
 template <int K> __device__ inline void keep_u64(uint64_t (&t)[K]);
 template <> __device__ inline void keep_u64<1>(uint64_t (&t)[1]) { asm("" : "+v"(t[0])); }
 template <> __device__ inline void keep_u64<2>(uint64_t (&t)[2]) { asm("" : "+v"(t[0]), "+v"(t[1])); }
@@ -130,6 +139,19 @@ template <> struct Phase<false> {
     args<1>({mx}, {my}, {mz}, {fx}, {fy}, {fz}, ux, uy, uz, a);
     return a[0];
   }
+  // K terms of one particle, each phase shifted by its offset (fixed-point d[c])
+  template <int K>
+  __device__ static inline void args_off(const int32_t (&mx)[K], const int32_t (&my)[K], const int32_t (&mz)[K],
+                                         const float (&)[K], const float (&)[K], const float (&)[K],
+                                         const uint64_t (&d)[K], const float (&)[K], Coord ux, Coord uy, Coord uz,
+                                         float (&a)[K]) {
+    uint64_t t[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) t[c] = phase_u64_off(mx[c], my[c], mz[c], ux, uy, uz, d[c]);
+    keep_u64<K>(t);
+#pragma unroll
+    for (int c = 0; c < K; ++c) a[c] = turns_arg((uint32_t)t[c]);
+  }
 };
 template <> struct Phase<true> {
   using Coord = float;
@@ -147,6 +169,15 @@ template <> struct Phase<true> {
                                      Coord uy, Coord uz, float (&a)[K]) {
 #pragma unroll
     for (int c = 0; c < K; ++c) a[c] = fmaf(fx[c], ux, fmaf(fy[c], uy, fz[c] * uz));
+  }
+  // shifted by the offset in turns (dt[c]), the first addend of the chain
+  template <int K>
+  __device__ static inline void args_off(const int32_t (&)[K], const int32_t (&)[K], const int32_t (&)[K],
+                                         const float (&fx)[K], const float (&fy)[K], const float (&fz)[K],
+                                         const uint64_t (&)[K], const float (&dt)[K], Coord ux, Coord uy, Coord uz,
+                                         float (&a)[K]) {
+#pragma unroll
+    for (int c = 0; c < K; ++c) a[c] = fmaf(fx[c], ux, fmaf(fy[c], uy, fmaf(fz[c], uz, dt[c])));
   }
 };
 
@@ -550,13 +581,10 @@ template <> struct KlParticle<false> { uint32_t ux, uy, uz; float q; };
 template <> struct KlParticle<true> { float ux, uy, uz; float q; };
 
 template <int TILE, int G, int KPL, bool VJP, bool FPH>
-__global__ __launch_bounds__(256) void rho_klane_kernel(WsView w, const double* __restrict__ x,
-                                                       const double* __restrict__ y,
-                                                       const double* __restrict__ z,
-                                                       const double* __restrict__ q,
-                                                       const int32_t* __restrict__ m,
-                                                       const float* __restrict__ gF, int64_t n_total,
-                                                       int32_t n_items) {
+__device__ __forceinline__ void rho_klane_body(const WsView& w, const double* __restrict__ x,
+                                               const double* __restrict__ y, const double* __restrict__ z,
+                                               const double* __restrict__ q, const int32_t* __restrict__ m,
+                                               const float* __restrict__ gF, int64_t n_total, int32_t n_items) {
   constexpr int KL = 64 / G;              // k-lanes per wave
   constexpr int PW = TILE / 4;            // particles per wave
   constexpr int STEPS = (PW + G - 1) / G; // particle steps of every lane
@@ -564,8 +592,9 @@ __global__ __launch_bounds__(256) void rho_klane_kernel(WsView w, const double* 
   using Ph = Phase<FPH>;
   using Pt = KlParticle<FPH>;
   static_assert(sizeof(Pt) == 16, "one 16-byte LDS read per particle");
-  __shared__ __align__(16) Pt tile[4 * PWP];
-  __shared__ __align__(16) float4 tgw[VJP ? 4 * PWP : 1];   // q gF of each slot (VJP)
+  // G slots past the last wave's are read (never used) by the two-step loop below
+  __shared__ __align__(16) Pt tile[4 * PWP + G];
+  __shared__ __align__(16) float4 tgw[VJP ? 4 * PWP + G : 1];   // q gF of each slot (VJP)
   __shared__ float red[4][G][2 * KPL][KL];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -621,14 +650,12 @@ __global__ __launch_bounds__(256) void rho_klane_kernel(WsView w, const double* 
 #pragma unroll
     for (int c = 0; c < 2 * KPL; ++c) acc[c] = 0.0f;
     if (g < G) {
-      // the same number of steps on every lane (zero slots pad the last one); the next
-      // particle is read from LDS while this one's terms are computed
+      // the same number of steps on every lane (zero slots pad the last one).  Forward pass:
+      // two steps per iteration, each particle read from LDS one step before its terms into
+      // one of two register sets that alternate, so no step copies a particle between them
       const Pt* tp = tile + wave * PWP + g;
       const float4* gp = tgw + (VJP ? wave * PWP + g : 0);
-      Pt nxt = tp[0];
-      for (int j = 0; j < STEPS; ++j) {
-        const Pt v = nxt;
-        if (j + 1 < STEPS) nxt = tp[(j + 1) * G];
+      auto step = [&](const Pt& v, int j) {
         float4 qg = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (VJP) qg = gp[j * G];
         float a[KPL], sn[KPL], cs[KPL];
@@ -643,6 +670,29 @@ __global__ __launch_bounds__(256) void rho_klane_kernel(WsView w, const double* 
           if (VJP) wt = fmaf(qg.x, fmx[c], fmaf(qg.y, fmy[c], qg.z * fmz[c]));
           acc[c] = fmaf(wt, cs[c], acc[c]);
           acc[KPL + c] = fmaf(wt, sn[c], acc[KPL + c]);
+        }
+      };
+      if constexpr (!VJP) {
+        Pt pa = tp[0];
+        int j = 0;
+        for (; j + 1 < STEPS; j += 2) {
+          const Pt pb = tp[(j + 1) * G];
+          step(pa, j);
+          // nothing moves across: pa's registers are free when its next value is read
+          __builtin_amdgcn_sched_barrier(0);
+          pa = tp[(j + 2) * G];   // slot (j + 2) G <= STEPS G: inside the padded tile
+          step(pb, j + 1);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if (STEPS & 1) step(pa, STEPS - 1);
+      } else {
+        // pass B1 carries more registers: one step per iteration, the next particle read
+        // while this one's terms are computed
+        Pt nxt = tp[0];
+        for (int j = 0; j < STEPS; ++j) {
+          const Pt v = nxt;
+          if (j + 1 < STEPS) nxt = tp[(j + 1) * G];
+          step(v, j);
         }
       }
 #pragma unroll
@@ -663,6 +713,26 @@ __global__ __launch_bounds__(256) void rho_klane_kernel(WsView w, const double* 
       part[2 * (kidx * sd.ntiles + it.tile) + comp] = sum;
     }
   }
+}
+
+// The forward k-lane pass keeps 8 waves per SIMD (64 VGPRs): a 1M-particle system's 1,954
+// blocks then fit in one round of 8 blocks per CU.  Pass B1 carries more registers.
+template <int TILE, int G, int KPL, bool FPH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void rho_klane_kernel(
+    WsView w, const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const double* __restrict__ q, const int32_t* __restrict__ m, int64_t n_total, int32_t n_items) {
+  rho_klane_body<TILE, G, KPL, false, FPH>(w, x, y, z, q, m, nullptr, n_total, n_items);
+}
+
+template <int TILE, int G, int KPL, bool FPH>
+__global__ __launch_bounds__(256) void rho_klane_vjp_kernel(WsView w, const double* __restrict__ x,
+                                                           const double* __restrict__ y,
+                                                           const double* __restrict__ z,
+                                                           const double* __restrict__ q,
+                                                           const int32_t* __restrict__ m,
+                                                           const float* __restrict__ gF, int64_t n_total,
+                                                           int32_t n_items) {
+  rho_klane_body<TILE, G, KPL, true, FPH>(w, x, y, z, q, m, gF, n_total, n_items);
 }
 
 // ------------------------------------------------------------------ rho pass, FP64 k-lane
@@ -875,8 +945,9 @@ __global__ __launch_bounds__(64 * WPB) void rho_f64_kernel(WsView w, const doubl
 // ------------------------------------------------------------------ cross-tile reduction
 
 // Force-pass row of wave vector g of system sd from the reduced rho (C, S): c_l from the
-// weight and |k_l|^2, and c_l times rho rotated by exp(-i delta) back onto the truncated
-// phases of the FP32-mixed form (delta = 0 otherwise).
+// weight and |k_l|^2, rho rotated by exp(-i delta) back onto the truncated phases of the
+// FP32-mixed form (delta = 0 otherwise), and from it the amplitude R_l and the phase offset
+// delta_l of the one-cosine form of the force term.
 __device__ inline ForceRowF32 force_row(const SysDesc& sd, int64_t g, const int32_t* __restrict__ m,
                                         const double* __restrict__ wk, double C, double S, double rot_c,
                                         double rot_s) {
@@ -888,11 +959,22 @@ __device__ inline ForceRowF32 force_row(const SysDesc& sd, int64_t g, const int3
   const double c = (k2 > 0.0) ? wk[g] * kFourPi / (vol * k2) : 0.0;
   const double Cr = C * rot_c + S * rot_s;
   const double Sr = S * rot_c - C * rot_s;
+  const double R = c * sqrt(Cr * Cr + Sr * Sr);
+  // delta = 1/4 - arg(rho') / (2 pi), reduced to [0, 1): R cos(theta + 2 pi delta)
+  // = R sin(arg(rho') - theta) = c (S' cos theta - C' sin theta)
+  double dl = 0.25 - atan2(Sr, Cr) / kTwoPi;
+  dl -= floor(dl);
+  if (!(dl >= 0.0 && dl < 1.0)) dl = 0.0;   // non-finite rho: R is NaN and carries it
   ForceRowF32 r;
+  r.d = (uint32_t)(uint64_t)llrint(dl * 4294967296.0);   // 2^32 wraps to 0
   r.mx = mx; r.my = my; r.mz = mz;
-  r.a = (float)(c * Sr);
-  r.b = (float)(c * Cr);
+  r.gx = r.hx = (float)(R * mx);
+  r.gy = r.hy = (float)(R * my);
+  r.gz = r.hz = (float)(R * mz);
+  r.pad0 = 0.0f;
   r.fx = (float)mx; r.fy = (float)my; r.fz = (float)mz;
+  r.dt = (float)dl;
+  r.r = (float)R;
   return r;
 }
 
@@ -1020,7 +1102,18 @@ __device__ inline double block_sum(double v, double* red) {
 
 // ------------------------------------------------------------------ force pass, FP32-mixed
 
-using TabF32 = ForceRowF32;   // the force kernel's LDS table rows
+// The force kernel's LDS table row: the two quarters of a ForceRowF32 that its form reads
+// (fixed-point phases: quarters 0 and 1; FP32 phases and the phase cache: 2 and 3; the
+// phase-cache pass stores m as float, c S', c C' instead).
+struct TabF32 { int4 lo, hi; };
+
+// A row as the phase-cache pass keeps it: (m as float, c S') and (c C', 0, 0, 0), where
+// c S' = R cos(2 pi delta) and c C' = R sin(2 pi delta).
+__device__ inline TabF32 cached_tab_row(int4 q2, int4 q3) {
+  const float dt = __int_as_float(q2.w), R = __int_as_float(q3.w);
+  const float a = R * __builtin_amdgcn_cosf(dt), b = R * __builtin_amdgcn_sinf(dt);
+  return TabF32{make_int4(q2.x, q2.y, q2.z, __float_as_int(a)), make_int4(__float_as_int(b), 0, 0, 0)};
+}
 
 template <int NPLF, bool CACHED, bool FPH>
 __global__ __launch_bounds__(kForceBlock) void force_f32_kernel(
@@ -1054,8 +1147,9 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
   // particles so that the two loads overlap.  The load is unconditional (a valid address for
   // every thread: a clamped row, or the system table when the system has no rows), so the
   // particle loads need not wait for it; only rows e < P are stored.
+  constexpr int kQ0 = (CACHED || FPH) ? 2 : 0;   // first quarter of a row this form reads
   const int4* rows = reinterpret_cast<const int4*>(frows + sd.k_off);
-  const int4* r0 = sd.p > 0 ? rows + 2 * min(tid, sd.p - 1) : reinterpret_cast<const int4*>(w.sys);
+  const int4* r0 = sd.p > 0 ? rows + 4 * min(tid, sd.p - 1) + kQ0 : reinterpret_cast<const int4*>(w.sys);
   const int4 row0a = r0[0], row0b = r0[1];
 
   using Ph = Phase<FPH>;
@@ -1080,11 +1174,7 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
   // the first chunk's rows go to LDS as soon as they arrive (once the previous item's
   // readers are done), which frees their registers before the particles are converted
   __syncthreads();
-  if (tid < min(kTabChunk, sd.p)) {
-    int4* dst = reinterpret_cast<int4*>(tab + tid);
-    dst[0] = row0a;
-    dst[1] = row0b;
-  }
+  if (tid < min(kTabChunk, sd.p)) tab[tid] = CACHED ? cached_tab_row(row0a, row0b) : TabF32{row0a, row0b};
 #pragma unroll
   for (int j = 0; j < NPLF; ++j) {
     if (j * kForceBlock + tid < it.np && !CACHED) {
@@ -1101,14 +1191,13 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
     if (t0 > 0) {
       __syncthreads();
       if (tid < cnt) {
-        int4* dst = reinterpret_cast<int4*>(tab + tid);
-        dst[0] = rows[2 * (t0 + tid)];
-        dst[1] = rows[2 * (t0 + tid) + 1];
+        const int4 lo = rows[4 * (t0 + tid) + kQ0], hi = rows[4 * (t0 + tid) + kQ0 + 1];
+        tab[tid] = CACHED ? cached_tab_row(lo, hi) : TabF32{lo, hi};
       }
     }
-    // zero rows pad the chunk to a multiple of kUnroll (m = 0, a = b = 0: no contribution)
+    // zero rows pad the chunk to a multiple of kUnroll (m = 0, R = a = b = 0: no contribution)
     const int cntp = (cnt + kUnroll - 1) / kUnroll * kUnroll;
-    for (int e = cnt + tid; e < cntp; e += kForceBlock) tab[e] = TabF32{0, 0, 0, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int e = cnt + tid; e < cntp; e += kForceBlock) tab[e] = TabF32{make_int4(0, 0, 0, 0), make_int4(0, 0, 0, 0)};
     __syncthreads();
     for (int e = 0; e < cntp; e += kUnroll) {
       TabF32 tb[kUnroll];
@@ -1116,8 +1205,10 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
       for (int u = 0; u < kUnroll; ++u) tb[u] = tab[e + u];
 #pragma unroll
       for (int j = 0; j < NPLF; ++j) {
-        float sn[kUnroll], cs[kUnroll];
         if (CACHED) {
+          // g = c (S' cos - C' sin) from the cached (cos, sin); quarters 2 and 3: m as float,
+          // c S', c C'
+          float sn[kUnroll], cs[kUnroll];
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) {
             if (j * kForceBlock + tid < it.np && e + u < cnt) {
@@ -1128,27 +1219,47 @@ for (int32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
               cs[u] = sn[u] = 0.0f;
             }
           }
-        } else {
-          float a[kUnroll];
-          int32_t rmx[kUnroll], rmy[kUnroll], rmz[kUnroll];
-          float rfx[kUnroll], rfy[kUnroll], rfz[kUnroll];
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) {
-            rmx[u] = tb[u].mx; rmy[u] = tb[u].my; rmz[u] = tb[u].mz;
-            rfx[u] = tb[u].fx; rfy[u] = tb[u].fy; rfz[u] = tb[u].fz;
+            const float g = __int_as_float(tb[u].lo.w) * cs[u] - __int_as_float(tb[u].hi.x) * sn[u];
+            fx[j] = fmaf(g, __int_as_float(tb[u].lo.x), fx[j]);
+            fy[j] = fmaf(g, __int_as_float(tb[u].lo.y), fy[j]);
+            fz[j] = fmaf(g, __int_as_float(tb[u].lo.z), fz[j]);
           }
-          Ph::template args<kUnroll>(rmx, rmy, rmz, rfx, rfy, rfz, ux[j], uy[j], uz[j], a);
+        } else {
+          // one cosine per term: m_l g = (R_l m_l) cos(theta + 2 pi delta_l), the offset
+          // entering the phase as its first addend
+          float a[kUnroll], gx[kUnroll], gy[kUnroll], gz[kUnroll];
+          int32_t rmx[kUnroll], rmy[kUnroll], rmz[kUnroll];
+          uint64_t rd[kUnroll];
+          float rfx[kUnroll], rfy[kUnroll], rfz[kUnroll], rdt[kUnroll];
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) sn[u] = __builtin_amdgcn_sinf(a[u]);
+          for (int u = 0; u < kUnroll; ++u) {
+            if (FPH) {   // quarter 2: m as float, delta in turns; quarter 3: R m
+              rfx[u] = __int_as_float(tb[u].lo.x); rfy[u] = __int_as_float(tb[u].lo.y);
+              rfz[u] = __int_as_float(tb[u].lo.z); rdt[u] = __int_as_float(tb[u].lo.w);
+              gx[u] = __int_as_float(tb[u].hi.x); gy[u] = __int_as_float(tb[u].hi.y);
+              gz[u] = __int_as_float(tb[u].hi.z);
+              rmx[u] = rmy[u] = rmz[u] = 0;
+              rd[u] = 0u;
+            } else {     // quarter 0: the offset and m; quarter 1: R m.  The 64-bit addend is
+                         // the register pair (d, m_x) as loaded: its high word does not reach
+                         // the low 32 bits of the sum, which are all the phase uses
+              rd[u] = ((uint64_t)(uint32_t)tb[u].lo.y << 32) | (uint32_t)tb[u].lo.x;
+              rmx[u] = tb[u].lo.y; rmy[u] = tb[u].lo.z; rmz[u] = tb[u].lo.w;
+              gx[u] = __int_as_float(tb[u].hi.x); gy[u] = __int_as_float(tb[u].hi.y);
+              gz[u] = __int_as_float(tb[u].hi.z);
+              rfx[u] = rfy[u] = rfz[u] = rdt[u] = 0.0f;
+            }
+          }
+          Ph::template args_off<kUnroll>(rmx, rmy, rmz, rfx, rfy, rfz, rd, rdt, ux[j], uy[j], uz[j], a);
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) cs[u] = __builtin_amdgcn_cosf(a[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const float g = tb[u].a * cs[u] - tb[u].b * sn[u];
-          fx[j] = fmaf(g, tb[u].fx, fx[j]);
-          fy[j] = fmaf(g, tb[u].fy, fy[j]);
-          fz[j] = fmaf(g, tb[u].fz, fz[j]);
+          for (int u = 0; u < kUnroll; ++u) {
+            const float cs = __builtin_amdgcn_cosf(a[u]);
+            fx[j] = fmaf(gx[u], cs, fx[j]);
+            fy[j] = fmaf(gy[u], cs, fy[j]);
+            fz[j] = fmaf(gz[u], cs, fz[j]);
+          }
         }
       }
     }
@@ -1638,8 +1749,12 @@ void launch_rho_klane_t(const LaunchShape& s, const WsView& w, const double* x, 
                         const double* z, const double* q, const int32_t* m, const float* gF, hipStream_t st) {
   int32_t blocks = s.n_rho_items;
   if (s.rho_grid_cap > 0) blocks = std::min<int32_t>(blocks, std::max<int32_t>((s.rho_grid_cap + 3) / 4, 1));
-  hipLaunchKernelGGL((rho_klane_kernel<TILE, G, KPL, VJP, FPH>), dim3((unsigned)std::max<int32_t>(blocks, 1)), dim3(256),
-                     0, st, w, x, y, z, q, m, gF, s.n_total, s.n_rho_items);
+  if constexpr (VJP)
+    hipLaunchKernelGGL((rho_klane_vjp_kernel<TILE, G, KPL, FPH>), dim3((unsigned)std::max<int32_t>(blocks, 1)),
+                       dim3(256), 0, st, w, x, y, z, q, m, gF, s.n_total, s.n_rho_items);
+  else
+    hipLaunchKernelGGL((rho_klane_kernel<TILE, G, KPL, FPH>), dim3((unsigned)std::max<int32_t>(blocks, 1)),
+                       dim3(256), 0, st, w, x, y, z, q, m, s.n_total, s.n_rho_items);
 }
 
 // Particle-tile pass over every (tile, k-range) item; VJP selects adjoint pass B1.
