@@ -5,12 +5,11 @@ water + 1 mol/L NaCl box (alpha = 0.06 / A^2, P = 100 wave vectors):
   draw P wave vectors on the device -> rho(k) pass -> cross-tile reduction ->
   force/energy pass.
 Inputs are resident in HBM before timing starts; nothing is skipped inside
-the timed region.  Back-to-back evaluations get faster over the first few
-hundred (0.094 ms after 10, 0.0856 ms after 300, then flat), so the default
-warm-up is 300 evaluations and the timed region is the steady state.  The headline value is the FP32-mixed form in
-G(particle*k)/s (N * P terms per evaluation); the FP64 form, the phase-cache
-variant, P = 200, the adjoint and the batched 128-replica form are timed
-beside it and reported in the same JSON line.
+the timed region.  The headline value is the FP32-mixed form in
+G(particle*k)/s (N * P terms per evaluation).  Timed beside it and reported in
+the same JSON line: the FP64 form, FP32 phases, the rho variant with
+compensated FP32 sums, the phase-cache variant, P = 200, the adjoint, the
+batched 128-replica form and the virial.
 
 roofline: FP32 vector arithmetic.  Peak = 256 CU x 128 FMA lanes x 2 FLOP x
 2.4 GHz = 157.3 TFLOP/s.  Algorithmic work per (particle, k) term in FP32 FMA
@@ -23,7 +22,9 @@ cpu_baseline: the FP64 oracle (plain C, OpenMP over independent outputs) on
 the same box, the same system and the same wave vectors, median of 3 full
 evaluations on all host threads and on one; it also gives the stated error of
 each GPU form (relative RMS force error and the largest per-particle error
-over the RMS force, energy and rho errors).
+over the RMS force, energy and rho errors), and on the 10M-atom electrolyte
+(all of rho, 4,000 sampled forces) the errors of FP32-mixed with plain and
+with compensated rho sums and of FP64.
 """
 from __future__ import annotations
 
@@ -50,10 +51,8 @@ FLOP_FORCE = 2 * (3 + 4 + 4 + 2 + 3)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    # the device settles after a few hundred evaluations (about 30 ms of work): the default
-    # warm-up covers that, so the timed steps measure the steady state of a long MD run
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--quick", action="store_true", help="skip the extra forms and the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true",
@@ -66,12 +65,16 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_form(torch, plan_cls, batch_cls, X, L, alpha, P, precision, phase_mode, steps, warmup, seed=2003):
+def run_form(torch, plan_cls, batch_cls, X, L, alpha, P, precision, phase_mode, steps, warmup, seed=2003,
+             rho_variant=None):
     """Time whole evaluations replayed from one captured HIP graph, then time the two
-    passes' kernels with HIP events placed around them on the launch stream."""
+    passes' kernels with HIP events placed around them on the launch stream.
+    rho_variant: replace the tuned rho variant (the tuned force variant is kept)."""
     n = X[0].numel()
     dev = X[0].device
     plan = plan_cls(batch_cls.single(n, P, L, alpha), precision=precision, phase_mode=phase_mode)
+    if rho_variant is not None:
+        plan.set_tiles(rho_variant, plan.tiles()[1])
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         counter = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -157,6 +160,14 @@ def main():
                                  "rho_kernel_ms": round(r["t_rho_s"] * 1e3, 4),
                                  "force_kernel_ms": round(r["t_force_s"] * 1e3, 4), "tiles": r["tiles"]}}
     if not args.quick:
+        comp = compensated_variant(Plan, Batch)
+        res["fp32_comp"] = r = run_form(torch, Plan, Batch, X, s.L, alpha, P, "fp32_mixed", "recompute", args.steps,
+                                        args.warmup, rho_variant=comp)
+        extra["fp32_mixed_compensated_P100"] = {"ms_per_step": round(r["wall_s"] * 1e3, 4),
+                                                "G_terms_per_s": round(terms / r["wall_s"] / 1e9, 3),
+                                                "rho_kernel_ms": round(r["t_rho_s"] * 1e3, 4),
+                                                "force_kernel_ms": round(r["t_force_s"] * 1e3, 4), "tiles": r["tiles"]}
+        log("compensated done")
         r = run_form(torch, Plan, Batch, X, s.L, alpha, P, "fp32_mixed", "cached", max(5, args.steps // 5), 3)
         extra["fp32_mixed_cached_phase_P100"] = {"ms_per_step": r["wall_s"] * 1e3, "G_terms_per_s": terms / r["wall_s"] / 1e9,
                                                  "rho_kernel_ms": r["t_rho_s"] * 1e3, "force_kernel_ms": r["t_force_s"] * 1e3}
@@ -221,6 +232,8 @@ def main():
     }
     if not args.quick and not args.no_cpu:
         out["cpu_baseline"], out["error_vs_oracle"] = cpu_baseline(s, P, res)
+        del X
+        out["error_vs_oracle"]["electrolyte_10M_P100"] = errors_10M(torch, ri, Plan, Batch, dev)
     print(json.dumps(out), flush=True)
 
 
@@ -318,7 +331,8 @@ def cpu_baseline(s, P, res):
                             "s_per_evaluation": round(t_one, 3), "sample": "the same evaluation, median of 3 runs"},
             "s_per_evaluation": round(t_all, 3), "cpu_model": model, "nproc": ncpu, "cpus_available": navail}
     errs = {}
-    for key, prec in (("fp32", "fp32_mixed"), ("fp64", "fp64"), ("fp32_phase", "fp32")):
+    for key, prec in (("fp32", "fp32_mixed"), ("fp64", "fp64"), ("fp32_phase", "fp32"),
+                      ("fp32_comp", "fp32_mixed_compensated")):
         if key not in res:
             continue
         r = res[key]
@@ -334,6 +348,55 @@ def cpu_baseline(s, P, res):
                       "energy_rel": float(abs(r["U"] - U_ref2) / abs(U_ref2)),
                       "rho_max_over_qnorm": float(np.max(np.abs(rc - rho_ref2)) / np.sqrt(np.sum(s.q ** 2)))}
     return base, errs
+
+
+def compensated_variant(Plan, Batch):
+    """Index of the FP32 rho variant with compensated sums."""
+    plan = Plan(Batch.single(1000, 8, 10.0, 0.5), precision="fp32_mixed", tiles=None)
+    nr, _ = plan.num_variants()
+    return next(v for v in range(nr) if plan.rho_variant_info(v)["compensated"] == 1)
+
+
+def errors_10M(torch, ri, Plan, Batch, dev):
+    """Errors of the FP32-mixed form (tuned rho variant and the compensated one) and of FP64 on
+    the 10M-atom electrolyte, P = 100, against the oracle: all of rho, the energy, and the
+    forces of 4,000 sampled particles (relative RMS and largest per-particle error over the
+    sample's RMS force)."""
+    import oracle
+    s, alpha, _ = ri.c3b_electrolyte()
+    P = 100
+    X = [torch.tensor(a, dtype=torch.float64, device=dev) for a in (s.x, s.y, s.z, s.q)]
+    comp = compensated_variant(Plan, Batch)
+    out, ref = {}, None
+    for name, prec, rv in (("fp32_mixed", "fp32_mixed", None), ("fp32_mixed_compensated", "fp32_mixed", comp),
+                           ("fp64", "fp64", None)):
+        plan = Plan(Batch.single(s.n, P, s.L, alpha), precision=prec)
+        if rv is not None:
+            plan.set_tiles(rv, plan.tiles()[1])
+        m, w = plan.sample_k_device(2004, 0)
+        F, U, rho = plan.forward(*X, m, w)
+        torch.cuda.synchronize()
+        mh, wh = m.cpu().numpy(), w.cpu().numpy()
+        if ref is None:
+            sel = np.sort(np.random.default_rng(8).choice(s.n, 4000, replace=False))
+            rho_ref = oracle.rho(s.x, s.y, s.z, s.q, mh, s.L)
+            F_ref = oracle.force_subset(s.x, s.y, s.z, s.q, mh, wh, s.L, rho_ref, sel)
+            k2 = np.sum((2 * np.pi * mh / s.L) ** 2, axis=1)
+            U_ref = float(np.sum(2 * np.pi / s.L ** 3 * wh / k2 * np.abs(rho_ref) ** 2))
+            ref = (mh, sel, rho_ref, F_ref, U_ref)
+        assert np.array_equal(mh, ref[0])   # the same device-drawn wave vectors in every form
+        _, sel, rho_ref, F_ref, U_ref = ref
+        Fs = F[:, torch.tensor(sel, device=dev)].double().cpu().numpy()
+        rc = rho[:, 0].cpu().numpy() + 1j * rho[:, 1].cpu().numpy()
+        dF = np.sqrt(np.sum((Fs - F_ref) ** 2, axis=0))
+        out[name] = {"tiles": plan.tiles(),
+                     "force_rel_rms_sampled": float(np.sqrt(np.sum((Fs - F_ref) ** 2) / np.sum(F_ref ** 2))),
+                     "force_max_particle_over_rms_sampled": float(dF.max() / np.sqrt(np.mean(np.sum(F_ref ** 2, axis=0)))),
+                     "energy_rel": float(abs(float(U.cpu()[0]) - U_ref) / abs(U_ref)),
+                     "rho_max_over_qnorm": float(np.max(np.abs(rc - rho_ref)) / np.sqrt(np.sum(s.q ** 2)))}
+        plan.close()
+        del F, U, rho
+    return out
 
 
 def bench_virial(torch, Plan, Batch, X, s, alpha, P, steps):

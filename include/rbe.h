@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define RBE_ABI_VERSION 2
+#define RBE_ABI_VERSION 3
 
 typedef enum {
     RBE_OK = 0,
@@ -170,18 +170,27 @@ rbe_status rbe_plan_get_tiles(const rbe_plan *plan, int32_t *rho_variant, int32_
 
 /*
  * Layout of rho variant `variant` of the plan's precision (0 <= variant < n_rho of
- * rbe_plan_num_variants), written to the four host int32 outputs:
- *   particles_per_lane: the tile is 64 x this many particles;
+ * rbe_plan_num_variants), written to the six host int32 outputs:
+ *   particles_per_lane: the per-wave layouts' tile is 64 x this many particles;
  *   vectors_per_chunk: wave vectors per inner-loop chunk (per lane in the k-lane layout);
  *   vectors_per_item: at most this many wave vectors per work item;
  *   waves_per_block: 4 (one item per wave), 16 (one block per CU sharing single-chunk
  *     items) or 1 (k-lane layout: one item per 256-thread block, wave vectors across
- *     the lanes).
+ *     the lanes);
+ *   particles_per_tile: particles per tile (64 x particles_per_lane, or for a k-lane
+ *     variant its own size; with the phase cache a k-lane variant uses 64 x
+ *     particles_per_lane);
+ *   compensated: 1 if the forward rho pass of the FP32 forms sums in compensated FP32
+ *     (runs of 16 terms per lane added into (hi, lo) pairs by TwoSum, pairs combined
+ *     within the block, FP64 only across tiles), 0 for plain FP32 per-lane sums of at
+ *     most 43 terms combined in FP64.  The adjoint pass B1 and the phase cache use the
+ *     plain sums.
  * RBE_EINVAL for a NULL pointer or a variant out of range.
  */
 rbe_status rbe_plan_rho_variant_info(const rbe_plan *plan, int32_t variant, int32_t *particles_per_lane,
                                      int32_t *vectors_per_chunk, int32_t *vectors_per_item,
-                                     int32_t *waves_per_block);
+                                     int32_t *waves_per_block, int32_t *particles_per_tile,
+                                     int32_t *compensated);
 
 /*
  * Persistent grids.  The rho-shaped passes run one wave per work item, four

@@ -29,7 +29,7 @@ SIGNATURES = {
     "rbe_plan_workspace_bytes": (_SZ, [_VP]),
     "rbe_plan_set_tiles": (_ST, [_VP, _I32, _I32]),
     "rbe_plan_num_variants": (_ST, [_VP, _VP, _VP]),
-    "rbe_plan_rho_variant_info": (_ST, [_VP, ctypes.c_int32, _VP, _VP, _VP, _VP]),
+    "rbe_plan_rho_variant_info": (_ST, [_VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP, _VP]),
     "rbe_plan_get_tiles": (_ST, [_VP, _VP, _VP]),
     "rbe_plan_destroy": (None, [_VP]),
     "rbe_plan_upload": (_ST, [_VP, _VP, _VP]),

@@ -143,7 +143,9 @@ namespace {
 void build_layout(rbe_plan* p) {
   const RhoVariant rv = p->rv();
   const ForceVariant fv = kForceVariants[p->force_variant];
-  const int tile = 64 * rv.npl;
+  // particles per rho tile; with the phase cache a k-lane variant runs the per-wave kernel,
+  // whose tiles are 64 npl particles
+  const int tile = (p->cached && rv.wpb == 1) ? 64 * rv.npl : rv.tile;
   const int fchunk = kForceBlock * fv.nplf;
   p->sys.assign(p->B, SysDesc{});
   p->rho_items.clear();
@@ -487,8 +489,8 @@ rbe_status rbe_plan_num_variants(const rbe_plan* p, int32_t* n_rho, int32_t* n_f
 }
 
 rbe_status rbe_plan_rho_variant_info(const rbe_plan* p, int32_t variant, int32_t* npl, int32_t* kc,
-                                     int32_t* krange, int32_t* wpb) {
-  if (!p || !npl || !kc || !krange || !wpb) return fail(RBE_EINVAL, "NULL argument");
+                                     int32_t* krange, int32_t* wpb, int32_t* tile, int32_t* comp) {
+  if (!p || !npl || !kc || !krange || !wpb || !tile || !comp) return fail(RBE_EINVAL, "NULL argument");
   const int nr = p->precision == RBE_FP64 ? kNumRhoVariantsF64 : kNumRhoVariantsF32;
   if (variant < 0 || variant >= nr) return fail(RBE_EINVAL, "rho variant %d out of range [0, %d)", variant, nr);
   const RhoVariant& rv = p->precision == RBE_FP64 ? kRhoVariantsF64[variant] : kRhoVariantsF32[variant];
@@ -496,6 +498,8 @@ rbe_status rbe_plan_rho_variant_info(const rbe_plan* p, int32_t variant, int32_t
   *kc = rv.kc;
   *krange = rv.krange;
   *wpb = rv.wpb;
+  *tile = (p->cached && rv.wpb == 1) ? 64 * rv.npl : rv.tile;
+  *comp = rv.comp;
   return RBE_OK;
 }
 

@@ -77,11 +77,12 @@ struct ForceItem {
 // items through LDS; krange is then one chunk) or 1 for the k-lane layout (one item per
 // 256-thread block, wave vectors across the lanes; "wave vectors per chunk" is then the
 // wave vectors per lane)
-struct RhoVariant { int npl; int kc; int krange; int wpb; };
+// tile: particles per tile; comp: compensated FP32 sums in the forward k-lane pass
+struct RhoVariant { int npl; int kc; int krange; int wpb; int tile; int comp; };
 struct ForceVariant { int nplf; };                       // particles per lane (256-thread blocks)
 
-constexpr int kNumRhoVariantsF32 = 11;
-constexpr int kNumRhoVariantsF64 = 9;
+constexpr int kNumRhoVariantsF32 = 13;
+constexpr int kNumRhoVariantsF64 = 10;
 constexpr int kNumForceVariants = 3;
 extern const RhoVariant kRhoVariantsF32[kNumRhoVariantsF32];
 extern const RhoVariant kRhoVariantsF64[kNumRhoVariantsF64];

@@ -31,18 +31,21 @@
 
 namespace rbe {
 
-// {particles per lane, wave vectors per chunk, wave vectors per work item}
+// {particles per lane, wave vectors per chunk, wave vectors per work item, waves per block,
+// particles per tile}
 const RhoVariant kRhoVariantsF32[kNumRhoVariantsF32] = {
-    {8, 8, 56, 4}, {8, 8, 40, 4}, {8, 8, 32, 4}, {8, 8, 104, 4}, {16, 8, 56, 4},
-    {8, 4, 28, 4}, {8, 4, 12, 4}, {8, 8, 8, 16}, {8, 4, 4, 16},
+    {8, 8, 56, 4, 512}, {8, 8, 40, 4, 512}, {8, 8, 32, 4, 512}, {8, 8, 104, 4, 512}, {16, 8, 56, 4, 1024},
+    {8, 4, 28, 4, 512}, {8, 4, 12, 4, 512}, {8, 8, 8, 16, 512}, {8, 4, 4, 16, 512},
     // k-lane layout (wpb 1: one item per 256-thread block): 5 wave vectors per lane, 3 x 21
-    // lanes, so an item covers up to 105 wave vectors; tiles of 512 and 256 particles
-    {8, 5, 105, 1}, {4, 5, 105, 1}};
+    // lanes, so an item covers up to 105 wave vectors; tiles of 512 and 256 particles, and of
+    // 492 = 4 waves x 41 steps x 3 (about 1M particles then fill 8 blocks per CU in one
+    // round); the last one with compensated FP32 sums (forward pass)
+    {8, 5, 105, 1, 512}, {4, 5, 105, 1, 256}, {8, 5, 105, 1, 492}, {8, 5, 105, 1, 492, 1}};
 const RhoVariant kRhoVariantsF64[kNumRhoVariantsF64] = {
-    {8, 4, 52, 4}, {8, 2, 50, 4}, {8, 2, 34, 4}, {8, 4, 36, 4}, {8, 4, 100, 4},
-    {4, 4, 100, 4}, {4, 8, 104, 4}, {4, 4, 4, 16},
-    // k-lane layout (wpb 1): 5 wave vectors on each of 3 x 21 lanes, 512-particle tiles
-    {8, 5, 105, 1}};
+    {8, 4, 52, 4, 512}, {8, 2, 50, 4, 512}, {8, 2, 34, 4, 512}, {8, 4, 36, 4, 512}, {8, 4, 100, 4, 512},
+    {4, 4, 100, 4, 256}, {4, 8, 104, 4, 256}, {4, 4, 4, 16, 256},
+    // k-lane layout (wpb 1): 5 wave vectors on each of 3 x 21 lanes, tiles of 512 and 492
+    {8, 5, 105, 1, 512}, {8, 5, 105, 1, 492}};
 const ForceVariant kForceVariants[kNumForceVariants] = {{1}, {2}, {4}};
 
 namespace {
@@ -580,7 +583,32 @@ template <bool FPH> struct KlParticle;
 template <> struct KlParticle<false> { uint32_t ux, uy, uz; float q; };
 template <> struct KlParticle<true> { float ux, uy, uz; float q; };
 
-template <int TILE, int G, int KPL, bool VJP, bool FPH>
+// Compensated FP32 sums (the COMP variant): runs of kCompBlock plain FP32 steps, each run's
+// sum then added into a per-lane (hi, lo) pair with an error-free TwoSum; the lane groups
+// and waves are combined as (hi, lo) pairs, so FP64 enters only across tiles.
+constexpr int kCompBlock = 16;
+
+// hi + lo += b: TwoSum of hi and b, its rounding error added to lo.
+__device__ inline void two_sum_into(float& hi, float& lo, float b) {
+  const float s = hi + b;
+  const float bb = s - hi;
+  const float e = (hi - (s - bb)) + (b - bb);
+  hi = s;
+  lo += e;
+}
+
+// (h, l) += (h2, l2) for unevaluated sums of two floats: TwoSum of the high parts, the low
+// parts added to its error, then renormalised (Fast2Sum).
+__device__ inline void pair_add(float& h, float& l, float h2, float l2) {
+  const float s = h + h2;
+  const float bb = s - h;
+  float e = (h - (s - bb)) + (h2 - bb);
+  e += l + l2;
+  h = s + e;
+  l = e - (h - s);
+}
+
+template <int TILE, int G, int KPL, bool VJP, bool FPH, bool COMP>
 __device__ __forceinline__ void rho_klane_body(const WsView& w, const double* __restrict__ x,
                                                const double* __restrict__ y, const double* __restrict__ z,
                                                const double* __restrict__ q, const int32_t* __restrict__ m,
@@ -595,7 +623,8 @@ __device__ __forceinline__ void rho_klane_body(const WsView& w, const double* __
   // G slots past the last wave's are read (never used) by the two-step loop below
   __shared__ __align__(16) Pt tile[4 * PWP + G];
   __shared__ __align__(16) float4 tgw[VJP ? 4 * PWP + G : 1];   // q gF of each slot (VJP)
-  __shared__ float red[4][G][2 * KPL][KL];
+  __shared__ float red[COMP ? 1 : 4][G][2 * KPL][KL];
+  __shared__ float2 redc[COMP ? 4 : 1][2 * KPL][KL];   // (hi, lo) per wave (COMP)
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -647,8 +676,13 @@ __device__ __forceinline__ void rho_klane_body(const WsView& w, const double* __
     }
     __syncthreads();
     float acc[2 * KPL];
+    float chi[COMP ? 2 * KPL : 1], clo[COMP ? 2 * KPL : 1];   // (hi, lo) pairs (COMP)
 #pragma unroll
     for (int c = 0; c < 2 * KPL; ++c) acc[c] = 0.0f;
+    if (COMP) {
+#pragma unroll
+      for (int c = 0; c < (COMP ? 2 * KPL : 1); ++c) chi[c] = clo[c] = 0.0f;
+    }
     if (g < G) {
       // the same number of steps on every lane (zero slots pad the last one).  Forward pass:
       // two steps per iteration, each particle read from LDS one step before its terms into
@@ -672,10 +706,12 @@ __device__ __forceinline__ void rho_klane_body(const WsView& w, const double* __
           acc[KPL + c] = fmaf(wt, sn[c], acc[KPL + c]);
         }
       };
-      if constexpr (!VJP) {
-        Pt pa = tp[0];
-        int j = 0;
-        for (; j + 1 < STEPS; j += 2) {
+      // steps j0 .. j1 - 1, two per iteration, each particle read one step before its terms
+      // into one of two register sets that alternate, so no step copies a particle
+      auto run = [&](int j0, int j1) {
+        Pt pa = tp[j0 * G];
+        int j = j0;
+        for (; j + 1 < j1; j += 2) {
           const Pt pb = tp[(j + 1) * G];
           step(pa, j);
           // nothing moves across: pa's registers are free when its next value is read
@@ -684,7 +720,21 @@ __device__ __forceinline__ void rho_klane_body(const WsView& w, const double* __
           step(pb, j + 1);
           __builtin_amdgcn_sched_barrier(0);
         }
-        if (STEPS & 1) step(pa, STEPS - 1);
+        if ((j1 - j0) & 1) step(pa, j1 - 1);
+      };
+      if constexpr (!VJP && !COMP) {
+        run(0, STEPS);
+      } else if constexpr (!VJP) {
+#pragma unroll
+        for (int c = 0; c < 2 * KPL; ++c) chi[c] = clo[c] = 0.0f;
+        for (int j0 = 0; j0 < STEPS; j0 += kCompBlock) {
+          run(j0, min(j0 + kCompBlock, STEPS));
+#pragma unroll
+          for (int c = 0; c < 2 * KPL; ++c) {
+            two_sum_into(chi[c], clo[c], acc[c]);
+            acc[c] = 0.0f;
+          }
+        }
       } else {
         // pass B1 carries more registers: one step per iteration, the next particle read
         // while this one's terms are computed
@@ -695,22 +745,50 @@ __device__ __forceinline__ void rho_klane_body(const WsView& w, const double* __
           step(v, j);
         }
       }
+      if constexpr (!COMP) {
 #pragma unroll
-      for (int c = 0; c < 2 * KPL; ++c) red[wave][g][c][kl] = acc[c];
+        for (int c = 0; c < 2 * KPL; ++c) red[wave][g][c][kl] = acc[c];
+      }
     }
-    __syncthreads();
-    // output o = (wave vector kk, component): the 4 G partial sums in a fixed order
     double* part = w.partials + 2 * sd.part_off;
-    for (int o = tid; o < 2 * it.nk; o += 256) {
-      const int kk = o >> 1, comp = o & 1;
-      const int c = kk / KL, r = kk % KL;
-      double sum = 0.0;
+    if constexpr (COMP) {
+      // the G lane groups of each k-lane (lanes kl, kl + KL, ...) as (hi, lo) pairs in a
+      // fixed order (lanes past the groups hold zeros), then the 4 waves; the pair becomes the
+      // tile's FP64 partial exactly
 #pragma unroll
-      for (int wv = 0; wv < 4; ++wv)
+      for (int c = 0; c < 2 * KPL; ++c) {
+        float h = chi[c], l = clo[c];
 #pragma unroll
-        for (int gg = 0; gg < G; ++gg) sum += (double)red[wv][gg][comp * KPL + c][r];
-      const int64_t kidx = it.k0 + kk;
-      part[2 * (kidx * sd.ntiles + it.tile) + comp] = sum;
+        for (int gg = 1; gg < G; ++gg) pair_add(h, l, __shfl(chi[c], kl + KL * gg, 64), __shfl(clo[c], kl + KL * gg, 64));
+        if (g == 0) redc[wave][c][kl] = make_float2(h, l);
+      }
+      __syncthreads();
+      for (int o = tid; o < 2 * it.nk; o += 256) {
+        const int kk = o >> 1, comp = o & 1;
+        const int c = kk / KL, r = kk % KL;
+        float2 v = redc[0][comp * KPL + c][r];
+#pragma unroll
+        for (int wv = 1; wv < 4; ++wv) {
+          const float2 u = redc[wv][comp * KPL + c][r];
+          pair_add(v.x, v.y, u.x, u.y);
+        }
+        const int64_t kidx = it.k0 + kk;
+        part[2 * (kidx * sd.ntiles + it.tile) + comp] = (double)v.x + (double)v.y;
+      }
+    } else {
+      __syncthreads();
+      // output o = (wave vector kk, component): the 4 G partial sums in a fixed order
+      for (int o = tid; o < 2 * it.nk; o += 256) {
+        const int kk = o >> 1, comp = o & 1;
+        const int c = kk / KL, r = kk % KL;
+        double sum = 0.0;
+#pragma unroll
+        for (int wv = 0; wv < 4; ++wv)
+#pragma unroll
+          for (int gg = 0; gg < G; ++gg) sum += (double)red[wv][gg][comp * KPL + c][r];
+        const int64_t kidx = it.k0 + kk;
+        part[2 * (kidx * sd.ntiles + it.tile) + comp] = sum;
+      }
     }
   }
 }
@@ -721,7 +799,15 @@ template <int TILE, int G, int KPL, bool FPH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void rho_klane_kernel(
     WsView w, const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const double* __restrict__ q, const int32_t* __restrict__ m, int64_t n_total, int32_t n_items) {
-  rho_klane_body<TILE, G, KPL, false, FPH>(w, x, y, z, q, m, nullptr, n_total, n_items);
+  rho_klane_body<TILE, G, KPL, false, FPH, false>(w, x, y, z, q, m, nullptr, n_total, n_items);
+}
+
+// The forward pass with compensated FP32 sums (more registers: 6 waves per SIMD).
+template <int TILE, int G, int KPL, bool FPH>
+__global__ __launch_bounds__(256) void rho_klane_comp_kernel(
+    WsView w, const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const double* __restrict__ q, const int32_t* __restrict__ m, int64_t n_total, int32_t n_items) {
+  rho_klane_body<TILE, G, KPL, false, FPH, true>(w, x, y, z, q, m, nullptr, n_total, n_items);
 }
 
 template <int TILE, int G, int KPL, bool FPH>
@@ -732,7 +818,7 @@ __global__ __launch_bounds__(256) void rho_klane_vjp_kernel(WsView w, const doub
                                                            const int32_t* __restrict__ m,
                                                            const float* __restrict__ gF, int64_t n_total,
                                                            int32_t n_items) {
-  rho_klane_body<TILE, G, KPL, true, FPH>(w, x, y, z, q, m, gF, n_total, n_items);
+  rho_klane_body<TILE, G, KPL, true, FPH, false>(w, x, y, z, q, m, gF, n_total, n_items);
 }
 
 // ------------------------------------------------------------------ rho pass, FP64 k-lane
@@ -1752,6 +1838,9 @@ void launch_rho_klane_t(const LaunchShape& s, const WsView& w, const double* x, 
   if constexpr (VJP)
     hipLaunchKernelGGL((rho_klane_vjp_kernel<TILE, G, KPL, FPH>), dim3((unsigned)std::max<int32_t>(blocks, 1)),
                        dim3(256), 0, st, w, x, y, z, q, m, gF, s.n_total, s.n_rho_items);
+  else if (s.rv.comp)
+    hipLaunchKernelGGL((rho_klane_comp_kernel<TILE, G, KPL, FPH>), dim3((unsigned)std::max<int32_t>(blocks, 1)),
+                       dim3(256), 0, st, w, x, y, z, q, m, s.n_total, s.n_rho_items);
   else
     hipLaunchKernelGGL((rho_klane_kernel<TILE, G, KPL, FPH>), dim3((unsigned)std::max<int32_t>(blocks, 1)),
                        dim3(256), 0, st, w, x, y, z, q, m, s.n_total, s.n_rho_items);
@@ -1765,9 +1854,11 @@ void tile_pass_f32(const LaunchShape& s, const WsView& w, const double* x, const
     case 10805:
     case 10405:
       // the k-lane layout (3 x 21 lanes, 5 wave vectors each) computes the forward pass and
-      // pass B1; the phase cache uses the per-wave kernel on the same tiles
+      // pass B1; the phase cache uses the per-wave kernel on the same tiles (of 64 npl
+      // particles: the plan gives k-lane variants those tiles in that mode)
       if constexpr (!CACHE) {
-        if (s.rv.npl == 8) launch_rho_klane_t<512, 3, 5, VJP, FPH>(s, w, x, y, z, q, m, g, st);
+        if (s.rv.tile == 512) launch_rho_klane_t<512, 3, 5, VJP, FPH>(s, w, x, y, z, q, m, g, st);
+        else if (s.rv.tile == 492) launch_rho_klane_t<492, 3, 5, VJP, FPH>(s, w, x, y, z, q, m, g, st);
         else launch_rho_klane_t<256, 3, 5, VJP, FPH>(s, w, x, y, z, q, m, g, st);
       } else {
         if (s.rv.npl == 8) launch_rho_f32_t<8, 8, CACHE, VJP, FPH, 4>(s, w, x, y, z, q, m, g, st);
@@ -1801,7 +1892,10 @@ void launch_tile_pass(const LaunchShape& s, const WsView& w, const double* x, co
   } else {
     const double* g = static_cast<const double*>(gF);
     switch (s.rv.wpb * 10000 + s.rv.npl * 100 + s.rv.kc) {
-      case 10805: launch_rho_klane_f64_t<512, 3, 5, VJP>(s, w, x, y, z, q, m, g, st); break;
+      case 10805:
+        if (s.rv.tile == 492) launch_rho_klane_f64_t<492, 3, 5, VJP>(s, w, x, y, z, q, m, g, st);
+        else launch_rho_klane_f64_t<512, 3, 5, VJP>(s, w, x, y, z, q, m, g, st);
+        break;
       case 160404: launch_rho_f64_t<4, 4, VJP, 16>(s, w, x, y, z, q, m, g, st); break;
       case 40804: launch_rho_f64_t<8, 4, VJP, 4>(s, w, x, y, z, q, m, g, st); break;
       case 40404: launch_rho_f64_t<4, 4, VJP, 4>(s, w, x, y, z, q, m, g, st); break;

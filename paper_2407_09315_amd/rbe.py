@@ -249,11 +249,11 @@ class Plan:
 
     def rho_variant_info(self, variant: int) -> dict:
         """Layout of a rho variant (rbe_plan_rho_variant_info); waves_per_block 1 is the k-lane layout."""
-        v = [ctypes.c_int32() for _ in range(4)]
+        v = [ctypes.c_int32() for _ in range(6)]
         check(self.lib.rbe_plan_rho_variant_info(self.handle, int(variant), *[ctypes.byref(x) for x in v]),
               "rbe_plan_rho_variant_info")
-        return dict(zip(("particles_per_lane", "vectors_per_chunk", "vectors_per_item", "waves_per_block"),
-                        (x.value for x in v)))
+        return dict(zip(("particles_per_lane", "vectors_per_chunk", "vectors_per_item", "waves_per_block",
+                         "particles_per_tile", "compensated"), (x.value for x in v)))
 
     @property
     def force_dtype(self):

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
     for name in names:
         assert hasattr(lib, name), name
         assert name in _lib.SIGNATURES, f"binding lacks {name}"
-    assert lib.rbe_abi_version() == 2
+    assert lib.rbe_abi_version() == 3
 
 
 _CTYPE_OF = {"int32_t": ctypes.c_int32, "uint64_t": ctypes.c_uint64, "double": ctypes.c_double,
@@ -154,16 +154,26 @@ def test_rho_variant_info():
         assert st == 0
         nr, nf = ctypes.c_int32(), ctypes.c_int32()
         assert lib.rbe_plan_num_variants(h, ctypes.byref(nr), ctypes.byref(nf)) == 0
-        v = [ctypes.c_int32() for _ in range(4)]
+        v = [ctypes.c_int32() for _ in range(6)]
+        n_comp = 0
         for r in range(nr.value):
             assert lib.rbe_plan_rho_variant_info(h, r, *[ctypes.byref(x) for x in v]) == 0
-            npl, kc, krange, wpb = (x.value for x in v)
+            npl, kc, krange, wpb, tile, comp = (x.value for x in v)
+            assert comp in (0, 1) and (comp == 0 or wpb == 1)
+            n_comp += comp
             assert wpb in (1, 4, 16) and npl in (4, 8, 16) and 1 <= kc <= krange
             if wpb == 1:
                 assert krange == 21 * kc   # 3 x 21 lanes, kc vectors each
+                # 4 waves, each a whole number of steps over its 3 particle groups
+                assert tile % 12 == 0 or tile == 64 * npl
+                assert tile <= 64 * npl
+            else:
+                assert tile == 64 * npl
+        # one compensated variant in the FP32 forms; FP64 sums need none
+        assert n_comp == (0 if prec == _lib.RBE_FP64 else 1)
         for bad in (-1, nr.value):
             assert lib.rbe_plan_rho_variant_info(h, bad, *[ctypes.byref(x) for x in v]) == _lib.RBE_EINVAL
-        assert lib.rbe_plan_rho_variant_info(h, 0, None, None, None, None) == _lib.RBE_EINVAL
+        assert lib.rbe_plan_rho_variant_info(h, 0, None, None, None, None, None, None) == _lib.RBE_EINVAL
         lib.rbe_plan_destroy(h)
 
 

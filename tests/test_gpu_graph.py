@@ -86,8 +86,8 @@ def test_persistent_grid_caps_bitwise(precision, schedule):
         assert torch.equal(F0, F1) and torch.equal(U0, U1) and torch.equal(r0, r1), caps
 
 
-@pytest.mark.parametrize("precision,rv", [("fp32_mixed", 9), ("fp32_mixed", 10), ("fp32", 9), ("fp32", 10),
-                                          ("fp64", 8)])
+@pytest.mark.parametrize("precision,rv", [("fp32_mixed", 9), ("fp32_mixed", 10), ("fp32_mixed", 11), ("fp32", 9),
+                                          ("fp32", 10), ("fp64", 8), ("fp64", 9)])
 def test_klane_grid_caps_bitwise(precision, rv):
     """The k-lane rho layouts under persistent grids (blocks striding over the items)."""
     s, alpha, _ = ri.c4_differentiable()

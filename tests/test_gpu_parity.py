@@ -93,13 +93,17 @@ def test_all_variants(precision):
 
 
 # the k-lane rho layouts (5 wave vectors on each of 3 x 21 lanes, one (tile, k-range) item
-# per block, at most 105 wave vectors per item): FP32 variants 9 (512-particle tiles) and
-# 10 (256), FP64 variant 8 (512)
+# per block, at most 105 wave vectors per item): FP32 variants 9 (512-particle tiles), 10
+# (256) and 11 (492), FP64 variants 8 (512) and 9 (492)
 KLANE = 9
 KLANE_256 = 10
+KLANE_492 = 11
+KLANE_COMP = 12      # 492-particle tiles, compensated FP32 sums in the forward pass
 KLANE_F64 = 8
-KLANE_CASES = [("fp32_mixed", KLANE), ("fp32_mixed", KLANE_256), ("fp32", KLANE), ("fp32", KLANE_256),
-               ("fp64", KLANE_F64)]
+KLANE_F64_492 = 9
+KLANE_CASES = [("fp32_mixed", KLANE), ("fp32_mixed", KLANE_256), ("fp32_mixed", KLANE_492),
+               ("fp32_mixed", KLANE_COMP), ("fp32", KLANE), ("fp32", KLANE_256), ("fp32", KLANE_492),
+               ("fp32", KLANE_COMP), ("fp64", KLANE_F64), ("fp64", KLANE_F64_492)]
 
 
 @pytest.mark.parametrize("precision,rv", KLANE_CASES)
@@ -112,7 +116,7 @@ def test_klane_layout(n, P, rv, precision):
     _check(f"k-lane{rv} n={n}", s, 0.35, P, 300 + P, precision, tiles=(rv, 0))
 
 
-@pytest.mark.parametrize("rv", [KLANE, KLANE_256])
+@pytest.mark.parametrize("rv", [KLANE, KLANE_256, KLANE_492, KLANE_COMP])
 def test_klane_layout_phase_cache(rv):
     """The phase cache with a k-lane variant selected runs the per-wave kernel on its items."""
     s = ri.random_charges(1300, 11.0, 71)

@@ -61,8 +61,8 @@ def test_vjp_vs_oracle_small(precision):
     _grad_check(precision, gr, gq, gr_ref, gq_ref)
 
 
-@pytest.mark.parametrize("precision,rv", [("fp32_mixed", 9), ("fp32_mixed", 10), ("fp32", 9), ("fp32", 10),
-                                          ("fp64", 8)])
+@pytest.mark.parametrize("precision,rv", [("fp32_mixed", 9), ("fp32_mixed", 10), ("fp32_mixed", 11),
+                                          ("fp32_mixed", 12), ("fp32", 9), ("fp32", 10), ("fp64", 8), ("fp64", 9)])
 def test_vjp_klane_variant(rv, precision):
     """With a k-lane rho layout selected, pass B1 runs in that layout."""
     s, alpha, P = ri.c1_small()
@@ -155,7 +155,7 @@ def test_device_sampler_bit_exact():
 
 # rho variants: the per-wave layout, and (FP32 forms) the two k-lane layouts
 BATCH_RHO = [("fp64", 0), ("fp32_mixed", 0), ("fp32", 0), ("fp32_mixed", 9), ("fp32_mixed", 10), ("fp32", 9),
-             ("fp64", 8)]
+             ("fp32_mixed", 11), ("fp32_mixed", 12), ("fp64", 8), ("fp64", 9)]
 
 
 @pytest.mark.parametrize("precision,rv", BATCH_RHO)
