@@ -97,6 +97,12 @@ typedef enum {
                                  pass reads them */
 } rbe_phase_mode;
 
+/* Device sampler of a plan (rbe_plan_set_sampler). */
+typedef enum {
+    RBE_SAMPLER_EXACT = 0,       /* exact i.i.d. draws (rbe_sample_k), the default */
+    RBE_SAMPLER_METROPOLIS = 1   /* the paper's Metropolis procedure (rbe_sample_k_metropolis) */
+} rbe_sampler;
+
 /*
  * A batch of B independent periodic cubic systems (all host memory, read only by
  * rbe_plan_create, which copies what it needs).  System b owns particles
@@ -131,6 +137,27 @@ typedef struct rbe_graph rbe_graph; /* opaque; an instantiated HIP graph of one 
  */
 rbe_status rbe_sample_k(uint64_t seed, uint64_t stream_id, double L, double alpha, int32_t P,
                         int32_t *m_out, double *w_out, double *S_out);
+
+/*
+ * Draw P wave-vector index triples with the Metropolis procedure the paper names
+ * for this step (Sec. 2.2; Alg. 1 step 1).  The paper fixes no proposal, start or
+ * burn-in; this chain (one per wave vector, the P chains independent):
+ *   target   exp(-pi^2 |m|^2 / (alpha L^2)) on Z^3 \ {0};
+ *   start    m = (1, 0, 0);
+ *   proposal m' = m + d, each d_j uniform on {-D..D}, D = max(1, ceil(1.5 sigma)),
+ *            sigma = L sqrt(alpha/2) / pi;
+ *   accept   m' != 0 and (|m'|^2 <= |m|^2 or u < exp(-pi^2 (|m'|^2 - |m|^2) / (alpha L^2)));
+ *   output   the state after burn_in steps.
+ * Step t of chain l draws Philox4x64-10 with key (seed, stream_id) and counter
+ * (l, t, 1, 0): d_j = min(floor(u_j (2D + 1)), 2D) - D from words 0..2, u from
+ * word 3 (u = (word >> 11) * 2^-53).  After a finite burn-in the draws are only
+ * approximately distributed as the target (64 steps reach it within the noise
+ * of 10^5 samples for the boxes of this library's workloads).  Outputs as for
+ * rbe_sample_k.  RBE_EINVAL for L <= 0, alpha <= 0, P < 0, burn_in < 0 or a
+ * NULL m_out with P > 0.
+ */
+rbe_status rbe_sample_k_metropolis(uint64_t seed, uint64_t stream_id, double L, double alpha, int32_t P,
+                                   int32_t burn_in, int32_t *m_out, double *w_out, double *S_out);
 
 /* S = (sum_m exp(-pi^2 m^2 / (alpha L^2)))^3 - 1 (the paper's Q). */
 rbe_status rbe_normalization(double L, double alpha, double *S_out);
@@ -293,11 +320,20 @@ rbe_status rbe_kspace_vjp(const rbe_plan *plan, const double *x, const double *y
                           double *gq, void *ws, void *stream);
 
 /*
+ * Choose the plan's device sampler: RBE_SAMPLER_EXACT (default) or
+ * RBE_SAMPLER_METROPOLIS with `burn_in` steps per chain (default 64).  Used by
+ * rbe_sample_k_device, rbe_evaluate, rbe_evaluate_static and graphs created
+ * afterwards.  RBE_EINVAL for another value or burn_in < 0.
+ */
+rbe_status rbe_plan_set_sampler(rbe_plan *plan, int32_t sampler, int32_t burn_in);
+
+/*
  * Draw the wave vectors of every system on the device: system b uses the
- * sampler of rbe_sample_k with key (seed + b, stream_id), so its rows of m
- * equal rbe_sample_k(seed + b, stream_id, L_b, alpha_b, P_b).  m: (dev)
- * P_total*3 int32; w: (dev) P_total FP64 receives S_b / P_b.  The plan
- * rejects systems whose zero-vector probability exceeds 1/2.
+ * plan's sampler with key (seed + b, stream_id), so its rows of m equal
+ * rbe_sample_k(seed + b, stream_id, L_b, alpha_b, P_b) (or
+ * rbe_sample_k_metropolis with the plan's burn-in).  m: (dev) P_total*3 int32;
+ * w: (dev) P_total FP64 receives S_b / P_b.  The plan rejects systems whose
+ * zero-vector probability exceeds 1/2.
  */
 rbe_status rbe_sample_k_device(const rbe_plan *plan, uint64_t seed, uint64_t stream_id,
                                int32_t *m, double *w, void *ws, void *stream);

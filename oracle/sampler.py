@@ -8,7 +8,8 @@ What is sampled (paper, Sec. 2.2 and Algorithm 1, step 1): P wave vectors
 k = 2 pi m / L, m in Z^3 \\ {0}, with probability proportional to
 exp(-k^2 / 4 alpha).  The paper draws them with a Metropolis chain; its
 unbiasedness statement assumes independent, identically distributed samples,
-so this build draws them exactly and independently:
+so the default sampler of this build draws them exactly and independently
+(the Metropolis variant is at the end of this module):
 
   * exp(-k^2/4 alpha) = prod_d exp(-beta m_d^2) with beta = pi^2 / (alpha L^2),
     so each component is an independent 1-D discrete Gaussian on Z with
@@ -140,3 +141,50 @@ def ewald_weights(m: np.ndarray, L: float, alpha: float) -> np.ndarray:
     k = 2.0 * np.pi * m.astype(np.float64) / L
     k2 = np.sum(k * k, axis=1)
     return np.exp(-k2 / (4.0 * alpha))
+
+
+# ---------------------------------------------------------------- Metropolis sampler
+#
+# The paper draws the P frequencies with the Metropolis procedure (Sec. 2.2; Algorithm 1,
+# step 1) without fixing its proposal, start, burn-in or thinning.  Reading used here:
+#   * one chain per wave vector l = 0..P-1, on Z^3 \ {0}, started at m = (1, 0, 0);
+#   * proposal m' = m + d, each component d_j uniform on {-D..D}, D = max(1, ceil(1.5 sigma));
+#   * target exp(-beta |m|^2) with beta = pi^2 / (alpha L^2) (that is exp(-k^2 / 4 alpha));
+#     m' = 0 is rejected; n = |m'|^2 - |m|^2 <= 0 is accepted; otherwise accepted when
+#     u < exp(-beta n);
+#   * B burn-in steps; the chain's state after step B is the sample (no thinning: the P
+#     chains are independent).
+# Step t of chain l uses Philox4x64-10 with key (seed, stream) and counter (l, t, 1, 0):
+# words 0..2 give the proposal, d_j = min(floor(u_j (2D + 1)), 2D) - D with
+# u_j = (word_j >> 11) 2^-53, and word 3 the acceptance uniform.
+
+METROPOLIS_BURN_IN = 64
+
+
+def metropolis_width(L: float, alpha: float) -> int:
+    return max(1, int(math.ceil(1.5 * sigma_of(L, alpha))))
+
+
+def metropolis_step(m, words, D: int, beta: float):
+    """One Metropolis step from m (a 3-list of ints) with the four Philox words of the step."""
+    u = [(w >> 11) * 2.0 ** -53 for w in words]
+    prop = [m[j] + min(int(math.floor(u[j] * (2 * D + 1))), 2 * D) - D for j in range(3)]
+    if prop == [0, 0, 0]:
+        return m
+    n = sum(v * v for v in prop) - sum(v * v for v in m)
+    if n <= 0 or u[3] < math.exp(-beta * float(n)):
+        return prop
+    return m
+
+
+def metropolis_k(seed: int, stream: int, L: float, alpha: float, P: int, burn_in: int = METROPOLIS_BURN_IN):
+    """P wave-vector index triples (P x 3 int32) from P Metropolis chains, and S."""
+    D = metropolis_width(L, alpha)
+    beta = beta_of(L, alpha)
+    out = np.zeros((P, 3), dtype=np.int32)
+    for l in range(P):
+        m = [1, 0, 0]
+        for t in range(burn_in):
+            m = metropolis_step(m, philox4x64_10((l, t, 1, 0), (seed, stream)), D, beta)
+        out[l] = m
+    return out, normalization_S(L, alpha)

@@ -17,12 +17,15 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librbe.so")
 RBE_OK, RBE_EINVAL, RBE_ENODEV, RBE_EHIP, RBE_EWORKSPACE, RBE_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 RBE_FP64, RBE_FP32_MIXED, RBE_FP32 = 0, 1, 2
 RBE_PHASE_AUTO, RBE_PHASE_RECOMPUTE, RBE_PHASE_CACHED = 0, 1, 2
+RBE_SAMPLER_EXACT, RBE_SAMPLER_METROPOLIS = 0, 1
 
 # name -> (restype, argtypes); every symbol that include/rbe.h declares
 _VP, _I32, _U64, _D, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t
 _ST = ctypes.c_int
 SIGNATURES = {
     "rbe_sample_k": (_ST, [_U64, _U64, _D, _D, _I32, _VP, _VP, _VP]),
+    "rbe_sample_k_metropolis": (_ST, [_U64, _U64, _D, _D, _I32, _I32, _VP, _VP, _VP]),
+    "rbe_plan_set_sampler": (_ST, [_VP, _I32, _I32]),
     "rbe_normalization": (_ST, [_D, _D, _VP]),
     "rbe_ewald_weights": (_ST, [_D, _D, _I32, _VP, _VP]),
     "rbe_plan_create": (_ST, [_VP, _I32, _I32, _VP]),

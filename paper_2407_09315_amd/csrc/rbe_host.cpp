@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "metropolis.h"
 #include "philox.h"
 #include "rbe.h"
 #include "rbe_internal.h"
@@ -110,6 +111,8 @@ struct rbe_plan {
   int32_t force_grid_cap = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // optional kernel timing events
   bool sampler_ok = true;
+  int32_t sampler = RBE_SAMPLER_EXACT;
+  int32_t burn_in = 64;
 
   // host copies of the device tables
   std::vector<SysDesc> sys;
@@ -220,7 +223,7 @@ void build_layout(rbe_plan* p) {
       }
     }
   }
-  // sampler tables: header (S, 2M+1, p, k_off) and c_-M .. c_M per system, fixed stride
+  // sampler tables: header (S, 2M+1, p, k_off, D, beta) and c_-M .. c_M per system, fixed stride
   p->sampler_ok = true;
   std::vector<ComponentTable> tabs((size_t)p->B);
   int64_t max_len = 0;
@@ -251,6 +254,8 @@ void build_layout(rbe_plan* p) {
     double* h = p->cdf.data() + (size_t)b * (size_t)p->cdf_stride;
     h[2] = s.p;
     h[3] = (double)s.k_off;
+    h[4] = (double)metropolis_width(p->L[b], p->alpha[b]);
+    h[5] = beta_of(p->L[b], p->alpha[b]);
     if (s.cdf_len == 0) continue;
     h[0] = normalization(p->L[b], p->alpha[b]);
     h[1] = s.cdf_len;
@@ -302,6 +307,8 @@ LaunchShape shape_of(const rbe_plan* p) {
   s.fv = kForceVariants[p->force_variant];
   s.force_variant = p->force_variant;
   s.cdf_stride = (int32_t)p->cdf_stride;
+  s.sampler = p->sampler;
+  s.burn_in = p->burn_in;
   s.rho_grid_cap = p->rho_grid_cap;
   s.rho_clamp = p->rho_clamp;
   s.force_grid_cap = p->force_grid_cap;
@@ -404,6 +411,37 @@ rbe_status rbe_sample_k(uint64_t seed, uint64_t stream_id, double L, double alph
     if (w_out) w_out[l] = S / (double)P;
   }
   if (S_out) *S_out = S;
+  return RBE_OK;
+}
+
+rbe_status rbe_sample_k_metropolis(uint64_t seed, uint64_t stream_id, double L, double alpha, int32_t P,
+                                   int32_t burn_in, int32_t* m_out, double* w_out, double* S_out) {
+  if (!finite_pos(L) || !finite_pos(alpha)) return fail(RBE_EINVAL, "L and alpha must be finite and > 0");
+  if (P < 0) return fail(RBE_EINVAL, "P must be >= 0 (got %d)", P);
+  if (burn_in < 0) return fail(RBE_EINVAL, "burn_in must be >= 0 (got %d)", burn_in);
+  if (P > 0 && m_out == nullptr) return fail(RBE_EINVAL, "m_out is NULL");
+  const int32_t D = metropolis_width(L, alpha);
+  const double beta = beta_of(L, alpha);
+  const double S = normalization(L, alpha);
+  for (int32_t l = 0; l < P; ++l) {
+    int32_t v[3];
+    metropolis_chain(seed, stream_id, (uint64_t)l, burn_in, D, beta, v);
+    m_out[3 * l] = v[0];
+    m_out[3 * l + 1] = v[1];
+    m_out[3 * l + 2] = v[2];
+    if (w_out) w_out[l] = S / (double)P;
+  }
+  if (S_out) *S_out = S;
+  return RBE_OK;
+}
+
+rbe_status rbe_plan_set_sampler(rbe_plan* p, int32_t sampler, int32_t burn_in) {
+  if (!p) return fail(RBE_EINVAL, "plan is NULL");
+  if (sampler != RBE_SAMPLER_EXACT && sampler != RBE_SAMPLER_METROPOLIS)
+    return fail(RBE_EINVAL, "unknown sampler %d", sampler);
+  if (burn_in < 0) return fail(RBE_EINVAL, "burn_in must be >= 0 (got %d)", burn_in);
+  p->sampler = sampler;
+  p->burn_in = burn_in;
   return RBE_OK;
 }
 

@@ -50,9 +50,10 @@ struct ForceRowF32 {
 };
 static_assert(sizeof(ForceRowF32) == 64, "ForceRowF32 layout");
 
-// Sampler table of system b: cdf[b * stride ...] = S, 2M+1, p, k_off (as doubles), then the
-// 2M+1 prefix sums (zero-padded to the stride), so a table's address needs no other lookup.
-constexpr int kCdfHeader = 4;
+// Sampler table of system b: cdf[b * stride ...] = S, 2M+1, p, k_off, then the Metropolis
+// chain's proposal half-width D and beta = pi^2 / (alpha L^2) (as doubles), then the 2M+1
+// prefix sums (zero-padded to the stride), so a table's address needs no other lookup.
+constexpr int kCdfHeader = 6;
 
 // rho-pass work item: one particle tile x one range of wave vectors.
 struct RhoItem {
@@ -118,6 +119,8 @@ struct LaunchShape {
   ForceVariant fv;
   int force_variant;
   int32_t cdf_stride;    // doubles per system in the sampler-table region
+  int32_t sampler;       // RBE_SAMPLER_EXACT or RBE_SAMPLER_METROPOLIS
+  int32_t burn_in;       // Metropolis steps per chain
   int32_t rho_grid_cap;  // persistent-grid caps (0: one block per work item)
   int32_t rho_clamp;     // 1: cap the rho-pass blocks per CU at their even share
   int32_t force_grid_cap;

@@ -25,6 +25,7 @@
 
 #include <algorithm>
 
+#include "metropolis.h"
 #include "philox.h"
 #include "rbe_internal.h"
 #include "sincos_coeffs.h"
@@ -1706,8 +1707,9 @@ __device__ inline void inverse_cdf3(const double* c, int32_t M, const double (&t
 
 __global__ __launch_bounds__(kSampleBlock) void sample_kernel(WsView w, uint64_t seed, uint64_t stream_base,
                                                               const uint64_t* __restrict__ counter,
-                                                              int32_t stride, int32_t in_lds,
-                                                              int32_t* __restrict__ m, double* __restrict__ wk) {
+                                                              int32_t stride, int32_t in_lds, int32_t sampler,
+                                                              int32_t burn_in, int32_t* __restrict__ m,
+                                                              double* __restrict__ wk) {
   extern __shared__ double table[];
   const int32_t b = blockIdx.x;
   // the stream id is stream_base plus the device step counter when one is given
@@ -1727,6 +1729,21 @@ __global__ __launch_bounds__(kSampleBlock) void sample_kernel(WsView w, uint64_t
   const double* c = h + kCdfHeader;
   const int32_t M = (len - 1) / 2;
   const double Z = c[2 * M];
+  if (sampler == RBE_SAMPLER_METROPOLIS) {
+    // one Metropolis chain per wave vector (the table is not read)
+    const int32_t D = (int32_t)h[4];
+    const double beta = h[5];
+    for (int32_t l = threadIdx.x; l < np; l += kSampleBlock) {
+      int32_t v[3];
+      metropolis_chain(seed + (uint64_t)b, stream_id, (uint64_t)l, burn_in, D, beta, v);
+      const int64_t g = k_off + l;
+      m[3 * g] = v[0];
+      m[3 * g + 1] = v[1];
+      m[3 * g + 2] = v[2];
+      wk[g] = S / (double)np;
+    }
+    return;
+  }
   for (int32_t l = threadIdx.x; l < np; l += kSampleBlock) {
     int32_t v[3] = {0, 0, 0};
     for (int a = 0; a < kMaxAttempts; ++a) {
@@ -2063,7 +2080,7 @@ hipError_t launch_sample(const LaunchShape& s, const WsView& w, uint64_t seed, u
   const int32_t in_lds = s.cdf_stride <= 8192 ? 1 : 0;
   hipLaunchKernelGGL(sample_kernel, dim3((unsigned)s.B), dim3(kSampleBlock),
                      in_lds ? sizeof(double) * (size_t)s.cdf_stride : 0, st, w, seed, stream_id, counter,
-                     s.cdf_stride, in_lds, m, wk);
+                     s.cdf_stride, in_lds, s.sampler, s.burn_in, m, wk);
   return hipGetLastError();
 }
 

@@ -80,6 +80,16 @@ def rbe_sample_k(seed: int, stream_id: int, L: float, alpha: float, P: int):
     return m, w, float(S[0])
 
 
+def rbe_sample_k_metropolis(seed: int, stream_id: int, L: float, alpha: float, P: int, burn_in: int = 64):
+    """(m (P, 3) int32, w (P,) float64 = S/P, S) from the library's Metropolis chains."""
+    m = np.zeros((P, 3), dtype=np.int32)
+    w = np.zeros(P, dtype=np.float64)
+    S = np.zeros(1, dtype=np.float64)
+    check(load().rbe_sample_k_metropolis(seed, stream_id, L, alpha, P, burn_in, _ptr(m), _ptr(w), _ptr(S)),
+          "rbe_sample_k_metropolis")
+    return m, w, float(S[0])
+
+
 def rbe_normalization(L: float, alpha: float) -> float:
     S = np.zeros(1, dtype=np.float64)
     check(load().rbe_normalization(L, alpha, _ptr(S)), "rbe_normalization")
@@ -207,6 +217,11 @@ class Plan:
         self._raw = raw
         self.ws = raw[off:off + nbytes]
         rbe_plan_upload(self.handle, self.ws)
+
+    def set_sampler(self, sampler: str = "exact", burn_in: int = 64):
+        """Device sampler: "exact" (i.i.d. draws) or "metropolis" (the paper's procedure)."""
+        code = {"exact": _lib.RBE_SAMPLER_EXACT, "metropolis": _lib.RBE_SAMPLER_METROPOLIS}[sampler]
+        check(self.lib.rbe_plan_set_sampler(self.handle, code, int(burn_in)), "rbe_plan_set_sampler")
 
     def set_tiles(self, rho_variant: int, force_variant: int):
         check(self.lib.rbe_plan_set_tiles(self.handle, rho_variant, force_variant), "rbe_plan_set_tiles")

@@ -206,3 +206,31 @@ def test_workspace_checks_and_nodev():
     if not torch.cuda.is_available():
         assert lib.rbe_plan_upload(h, ctypes.c_void_p(1024), None) == _lib.RBE_ENODEV
     lib.rbe_plan_destroy(h)
+
+
+@pytest.mark.parametrize("seed,stream,L,alpha,P,burn_in", [
+    (2001, 0, 31.0, 0.1, 100, 64),
+    (2003, 7, 217.0535, 0.06, 50, 64),
+    (2004, 1, 467.6275, 0.06, 30, 40),
+    (7, 2 ** 63 + 3, 2.0, 1.5, 60, 64),      # tiny box: most proposals rejected
+    (2 ** 64 - 1, 5, 10.0, 0.362, 40, 0),   # no step: every chain at its start
+])
+def test_host_metropolis_bit_exact_vs_oracle(seed, stream, L, alpha, P, burn_in):
+    m, w, S = rbe.rbe_sample_k_metropolis(seed, stream, L, alpha, P, burn_in)
+    m_ref, S_ref = oracle.sampler.metropolis_k(seed, stream, L, alpha, P, burn_in)
+    assert np.array_equal(m, m_ref)
+    assert not np.any(np.all(m == 0, axis=1))
+    assert abs(S / S_ref - 1) < 1e-14 and np.all(w == S / P)
+
+
+def test_metropolis_argument_checks():
+    lib = _lib.load()
+    assert lib.rbe_sample_k_metropolis(1, 0, 10.0, 0.3, 4, -1, None, None, None) == _lib.RBE_EINVAL
+    assert lib.rbe_sample_k_metropolis(1, 0, -1.0, 0.3, 4, 8, None, None, None) == _lib.RBE_EINVAL
+    st, h = _create(1, [0, 10], [0, 5], [3.0], [1.0])
+    assert st == 0
+    assert lib.rbe_plan_set_sampler(h, 2, 10) == _lib.RBE_EINVAL
+    assert lib.rbe_plan_set_sampler(h, _lib.RBE_SAMPLER_METROPOLIS, -3) == _lib.RBE_EINVAL
+    assert lib.rbe_plan_set_sampler(h, _lib.RBE_SAMPLER_METROPOLIS, 16) == 0
+    assert lib.rbe_plan_set_sampler(None, 0, 0) == _lib.RBE_EINVAL
+    lib.rbe_plan_destroy(h)

@@ -108,3 +108,114 @@ def test_window_mass_below_double_resolution():
         tail = 2 * sum(math.exp(-beta * j * j) for j in range(M + 1, M + 400))
         total = sum(math.exp(-beta * j * j) for j in range(-M - 400, M + 400))
         assert tail / total < 2.0 ** -53
+
+
+# ---------------------------------------------------------------- Metropolis variant
+#
+# The paper samples with the Metropolis procedure (Sec. 2.2; Algorithm 1, step 1) but
+# fixes no proposal, start or burn-in; the oracle's chain follows the reading written in
+# oracle/sampler.py.  Pins:
+#   * one step from fixed states: the distribution of the next state over many Philox
+#     counters against the transition probabilities of a symmetric uniform proposal with
+#     acceptance min(1, pi(m') / pi(m)), pi evaluated from the density in k;
+#   * the kernel those probabilities define leaves pi invariant (detailed balance, checked
+#     numerically on every pair of states of a box);
+#   * after the burn-in, the chains' outputs against the exact pmf of |m|^2 (chi-square).
+
+
+def _pi_k(m, L, alpha):
+    k = 2.0 * np.pi * np.asarray(m, dtype=np.float64) / L
+    return np.exp(-np.sum(k * k, axis=-1) / (4.0 * alpha))
+
+
+def _one_step_probs(m0, L, alpha, D):
+    """Exact next-state probabilities of one step from m0: {state tuple: probability}."""
+    m0 = np.asarray(m0)
+    r = np.arange(-D, D + 1)
+    d = np.stack(np.meshgrid(r, r, r, indexing="ij"), axis=-1).reshape(-1, 3)
+    prop = m0 + d
+    p_prop = 1.0 / len(d)
+    ratio = _pi_k(prop, L, alpha) / _pi_k(m0, L, alpha)
+    acc = np.where(np.all(prop == 0, axis=1), 0.0, np.minimum(1.0, ratio))
+    out = {}
+    for mp, a in zip(map(tuple, prop), acc):
+        if a > 0:
+            out[mp] = out.get(mp, 0.0) + p_prop * a
+    out[tuple(m0)] = out.get(tuple(m0), 0.0) + p_prop * float(np.sum(1.0 - acc))
+    return out
+
+
+@pytest.mark.parametrize("m0", [(1, 0, 0), (3, -2, 1), (0, 0, -1)])
+def test_metropolis_one_step_distribution(m0):
+    L, alpha = 31.0, 0.1
+    D = sampler.metropolis_width(L, alpha)
+    beta = sampler.beta_of(L, alpha)
+    n = 60000
+    counts = {}
+    for l in range(n):
+        nxt = tuple(sampler.metropolis_step(list(m0), sampler.philox4x64_10((l, 0, 1, 0), (9, 4)), D, beta))
+        counts[nxt] = counts.get(nxt, 0) + 1
+    probs = _one_step_probs(m0, L, alpha, D)
+    assert set(counts) <= set(probs)          # never a state the kernel cannot reach (nor 0)
+    keys = sorted(probs, key=lambda s: -probs[s])
+    exp = np.array([probs[s] * n for s in keys])
+    obs = np.array([counts.get(s, 0) for s in keys], dtype=np.float64)
+    big = exp >= 5
+    e = np.append(exp[big], exp[~big].sum())
+    o = np.append(obs[big], obs[~big].sum())
+    chi2 = float(np.sum((o - e) ** 2 / e))
+    assert stats.chi2.sf(chi2, len(e) - 1) > 1e-4, chi2
+
+
+def test_metropolis_detailed_balance():
+    """pi(m) T(m -> m') = pi(m') T(m' -> m) for every pair of states in a box (so pi is
+    stationary), with T the one-step probabilities the first pin checks the chain against."""
+    L, alpha = 31.0, 0.1
+    D = sampler.metropolis_width(L, alpha)
+    r = range(-3, 4)
+    states = [(a, b, c) for a in r for b in r for c in r if (a, b, c) != (0, 0, 0)]
+    T = {s: _one_step_probs(s, L, alpha, D) for s in states}
+    for s in states:
+        for t, p in T[s].items():
+            if t in T and t != s:
+                lhs = _pi_k(s, L, alpha) * p
+                rhs = _pi_k(t, L, alpha) * T[t].get(s, 0.0)
+                assert abs(lhs - rhs) <= 1e-15 * max(lhs, rhs, 1e-300), (s, t)
+        assert abs(sum(T[s].values()) - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("L,alpha", [(31.0, 0.1), (66.9, 0.048)])
+def test_metropolis_output_chi_square(L, alpha):
+    """After the default burn-in the chains' states follow pi: |m|^2 against its exact pmf."""
+    P = 2500
+    samples = np.concatenate([sampler.metropolis_k(101 + s, s, L, alpha, P)[0] for s in range(2)])
+    assert not np.any(np.all(samples == 0, axis=1))
+    M = sampler.window_of(L, alpha)
+    r = np.arange(-M, M + 1)
+    g = np.stack(np.meshgrid(r, r, r, indexing="ij"), axis=-1).reshape(-1, 3)
+    g = g[np.any(g != 0, axis=1)]
+    pk = _pi_k(g, L, alpha)
+    s2 = np.sum(g * g, axis=1)
+    # |m|^2 in bins of about equal probability
+    order = np.argsort(s2)
+    cum = np.cumsum(pk[order]) / pk.sum()
+    edges = [0]
+    for q in np.linspace(0.05, 0.95, 19):
+        edges.append(int(s2[order][np.searchsorted(cum, q)]))
+    edges = sorted(set(edges)) + [int(s2.max()) + 1]
+    exp = np.array([pk[(s2 >= a) & (s2 < b)].sum() for a, b in zip(edges[:-1], edges[1:])]) / pk.sum()
+    ss = np.sum(samples.astype(np.int64) ** 2, axis=1)
+    obs = np.array([np.sum((ss >= a) & (ss < b)) for a, b in zip(edges[:-1], edges[1:])], dtype=np.float64)
+    e = exp * len(ss)
+    chi2 = float(np.sum((obs - e) ** 2 / e))
+    assert stats.chi2.sf(chi2, len(e) - 1) > 1e-4, (chi2, len(e))
+
+
+def test_metropolis_start_and_determinism():
+    m, S = sampler.metropolis_k(5, 1, 31.0, 0.1, 7, burn_in=0)
+    assert np.all(m == np.array([1, 0, 0]))
+    a, _ = sampler.metropolis_k(5, 1, 31.0, 0.1, 20)
+    b, _ = sampler.metropolis_k(5, 1, 31.0, 0.1, 20)
+    c, _ = sampler.metropolis_k(5, 2, 31.0, 0.1, 20)
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    assert abs(S / sampler.normalization_S(31.0, 0.1) - 1) == 0
