@@ -7,7 +7,10 @@ loads or calls it, and it imports nothing from the product package.
 Contents:
   * ``rbe_oracle.c`` -- plain FP64 definitions of rho(k), the RBE / Ewald
     k-space force, energy and virial tensor, their vector-Jacobian product,
-    and the real-space + self Ewald energy, compiled with gcc into
+    and the real-space + self Ewald energy;
+  * ``rbl_oracle.c`` -- the random batch list (RBL) short-range force (core
+    sum, shell batch, momentum correction) by brute force over all pairs, and
+    the truncated short-range energy; both compiled with gcc into
     ``liboracle.so``;
   * ``sampler.py`` -- the exact i.i.d. wave-vector sampler, Philox4x64-10 and
     the normalisation S, in plain Python;
@@ -32,7 +35,7 @@ from . import sampler  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SRC = os.path.join(_HERE, "rbe_oracle.c")
+_SRCS = [os.path.join(_HERE, "rbe_oracle.c"), os.path.join(_HERE, "rbl_oracle.c")]
 _lib = None
 
 
@@ -41,7 +44,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-               "-fno-fast-math", "-o", tmp, _SRC, "-lm"]
+               "-fno-fast-math", "-o", tmp, *_SRCS, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -64,6 +67,10 @@ def _load():
         lib.oracle_vjp.argtypes = [i64, P, P, P, P, i64, P, P, d, d, P, P, P, P]
         lib.oracle_ewald_real_self.argtypes = [i64, P, P, P, P, d, d, i32, P, P]
         lib.oracle_virial.argtypes = [i64, P, P, d, d, P, P]
+        lib.oracle_rbl_short_force.restype = ctypes.c_int
+        lib.oracle_rbl_short_force.argtypes = [i64, P, P, P, P, P, P, d, d, d, d, i32, P, P, P]
+        lib.oracle_short_energy.restype = d
+        lib.oracle_short_energy.argtypes = [i64, P, P, P, P, P, P, d, d, d]
         _lib = lib
     return _lib
 
@@ -154,3 +161,32 @@ def virial(m, w, L, alpha, rho_c):
     W = np.zeros(6)
     _load().oracle_virial(m.shape[0], _ptr(m), _ptr(w), float(L), float(alpha), _ptr(rho), _ptr(W))
     return W
+
+
+def rbl_offsets(seed: int, step: int, n: int) -> np.ndarray:
+    """Batch offsets u_i in [0, 1) of the RBL shell batches: word 0 of Philox4x64-10 with
+    key (seed, step) and counter (i, 0, 3, 0), top 53 bits."""
+    out = np.empty(n, dtype=np.float64)
+    for i in range(n):
+        out[i] = (sampler.philox4x64_10((i, 0, 3, 0), (seed, step))[0] >> 11) * 2.0 ** -53
+    return out
+
+
+def rbl_short_force(x, y, z, q, eps, sig, L, alpha, rc, rs, p, u):
+    """RBL short-range force (F (3, N), N_s (N,)) with batch offsets u (N,)."""
+    x, y, z, q, eps, sig, u = map(_f64, (x, y, z, q, eps, sig, u))
+    n = q.shape[0]
+    F = np.zeros(3 * n)
+    ns = np.zeros(n, dtype=np.int64)
+    st = _load().oracle_rbl_short_force(n, _ptr(x), _ptr(y), _ptr(z), _ptr(q), _ptr(eps), _ptr(sig), float(L),
+                                        float(alpha), float(rc), float(rs), int(p), _ptr(u), _ptr(F), _ptr(ns))
+    if st != 0:
+        raise ValueError(f"oracle_rbl_short_force failed ({st}): need 0 < rc <= rs < L/2 and p >= 1")
+    return F.reshape(3, n), ns
+
+
+def short_energy(x, y, z, q, eps, sig, L, alpha, rs):
+    """Short-range energy (LJ + real-space Coulomb) of every pair inside rs."""
+    x, y, z, q, eps, sig = map(_f64, (x, y, z, q, eps, sig))
+    return float(_load().oracle_short_energy(q.shape[0], _ptr(x), _ptr(y), _ptr(z), _ptr(q), _ptr(eps),
+                                             _ptr(sig), float(L), float(alpha), float(rs)))

@@ -210,3 +210,39 @@ def c5_replicas(B: int = 128, seed_base: int = 5000, P: int = 100) -> Replicas:
         systems.append(uniform_pm1(n, L, seed_base + 100_000 + b))
         alphas.append(alpha)
     return Replicas(systems, alphas, P)
+
+
+# ---------------------------------------------------------------- short-range (RBL) systems
+
+@dataclasses.dataclass
+class LJSystem:
+    """Charged Lennard-Jones particles: positions, charges and per-particle LJ eps, sigma."""
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+    q: np.ndarray
+    eps: np.ndarray
+    sig: np.ndarray
+    L: float
+
+    @property
+    def n(self) -> int:
+        return int(self.q.shape[0])
+
+
+def primitive_electrolyte(n: int, density: float, seed: int, jitter: float = 0.25) -> LJSystem:
+    """The paper's primitive-model 1:1 electrolyte (Sec. 4): n/2 cations (+1) and n/2 anions
+    (-1), LJ eps = sigma = 1 (reduced units), at `density` particles per sigma^3.  Positions:
+    a simple cubic lattice of spacing a = L / ceil(n^(1/3)) filled in random order, each
+    site moved by a uniform random offset of up to jitter * a per axis (no overlaps, a
+    liquid-like spread of distances)."""
+    g = _rng(seed)
+    L = (n / density) ** (1.0 / 3.0)
+    side = int(math.ceil(n ** (1.0 / 3.0)))
+    a = L / side
+    sites = np.stack(np.meshgrid(*(np.arange(side),) * 3, indexing="ij"), axis=-1).reshape(-1, 3)
+    pick = g.permutation(sites.shape[0])[:n]
+    pos = (sites[pick] + 0.5 + g.uniform(-jitter, jitter, size=(n, 3))) * a
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    g.shuffle(q)
+    return LJSystem(pos[:, 0].copy(), pos[:, 1].copy(), pos[:, 2].copy(), q, np.ones(n), np.ones(n), float(L))
