@@ -69,6 +69,8 @@ def _load():
         lib.oracle_virial.argtypes = [i64, P, P, d, d, P, P]
         lib.oracle_rbl_short_force.restype = ctypes.c_int
         lib.oracle_rbl_short_force.argtypes = [i64, P, P, P, P, P, P, d, d, d, d, i32, P, P, P]
+        lib.oracle_rbl_raw_subset.restype = ctypes.c_int
+        lib.oracle_rbl_raw_subset.argtypes = [i64, P, P, P, P, P, P, d, d, d, d, i32, i64, P, P, P, P]
         lib.oracle_short_energy.restype = d
         lib.oracle_short_energy.argtypes = [i64, P, P, P, P, P, P, d, d, d]
         _lib = lib
@@ -163,13 +165,28 @@ def virial(m, w, L, alpha, rho_c):
     return W
 
 
-def rbl_offsets(seed: int, step: int, n: int) -> np.ndarray:
+def rbl_offsets(seed: int, step: int, n, ) -> np.ndarray:
     """Batch offsets u_i in [0, 1) of the RBL shell batches: word 0 of Philox4x64-10 with
-    key (seed, step) and counter (i, 0, 3, 0), top 53 bits."""
-    out = np.empty(n, dtype=np.float64)
-    for i in range(n):
-        out[i] = (sampler.philox4x64_10((i, 0, 3, 0), (seed, step))[0] >> 11) * 2.0 ** -53
-    return out
+    key (seed, step) and counter (i, 0, 3, 0), top 53 bits.  n: a count (particles 0..n-1)
+    or an array of particle indices."""
+    idx = range(n) if isinstance(n, (int, np.integer)) else [int(i) for i in n]
+    return np.array([(sampler.philox4x64_10((i, 0, 3, 0), (seed, step))[0] >> 11) * 2.0 ** -53 for i in idx],
+                    dtype=np.float64)
+
+
+def rbl_raw_subset(x, y, z, q, eps, sig, L, alpha, rc, rs, p, sel, u_sel):
+    """Raw RBL forces (before the momentum correction) of the particles sel: ((3, m), N_s (m,))."""
+    x, y, z, q, eps, sig, u_sel = map(_f64, (x, y, z, q, eps, sig, u_sel))
+    sel = np.ascontiguousarray(sel, dtype=np.int64)
+    m = sel.shape[0]
+    out = np.zeros(3 * m)
+    ns = np.zeros(m, dtype=np.int64)
+    st = _load().oracle_rbl_raw_subset(q.shape[0], _ptr(x), _ptr(y), _ptr(z), _ptr(q), _ptr(eps), _ptr(sig),
+                                       float(L), float(alpha), float(rc), float(rs), int(p), m, _ptr(sel),
+                                       _ptr(u_sel), _ptr(out), _ptr(ns))
+    if st != 0:
+        raise ValueError(f"oracle_rbl_raw_subset failed ({st})")
+    return out.reshape(3, m), ns
 
 
 def rbl_short_force(x, y, z, q, eps, sig, L, alpha, rc, rs, p, u):

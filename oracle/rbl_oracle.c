@@ -108,6 +108,57 @@ static int cmp_entry(const void *a, const void *b) {
 }
 
 /*
+ * Raw RBL force of particle i, F_i^core + F_i^shell* (Eqs. short, fshell), by brute force
+ * over all particles; sh: scratch for n entries.  Returns N_s.
+ */
+static int64_t rbl_raw_one(int64_t i, int64_t n, const double *x, const double *y, const double *z, const double *q,
+                           const double *eps, const double *sig, double L, double alpha, double rc2, double rs2,
+                           int32_t p, double u, const grid *g, shell_entry *sh, double out[3]) {
+    const double pi_[3] = {x[i], y[i], z[i]};
+    const int64_t ci[3] = {cell_of(x[i], L, g->nc), cell_of(y[i], L, g->nc), cell_of(z[i], L, g->nc)};
+    rsum core[3] = {{0, 0}, {0, 0}, {0, 0}};
+    int64_t ns = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        const double pj[3] = {x[j], y[j], z[j]};
+        double d[3];
+        for (int k = 0; k < 3; ++k) d[k] = min_image(pi_[k] - pj[k], L);
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (r2 < rc2) {
+            double f[3];
+            pair_force(q[i], q[j], eps[i], eps[j], sig[i], sig[j], alpha, d, r2, f);
+            for (int k = 0; k < 3; ++k) rsum_add(&core[k], f[k]);
+        } else if (r2 <= rs2) {
+            const int64_t cj[3] = {cell_of(x[j], L, g->nc), cell_of(y[j], L, g->nc), cell_of(z[j], L, g->nc)};
+            const int64_t s = (stencil_pos(ci[0], cj[0], g) * g->span + stencil_pos(ci[1], cj[1], g)) * g->span +
+                              stencil_pos(ci[2], cj[2], g);
+            sh[ns].key = s * n + j;
+            sh[ns].j = j;
+            ++ns;
+        }
+    }
+    qsort(sh, (size_t)ns, sizeof(shell_entry), cmp_entry);
+    rsum shell[3] = {{0, 0}, {0, 0}, {0, 0}};
+    const double wgt = ns > p ? (double)ns / (double)p : 1.0;
+    const int64_t nb = ns > p ? p : ns;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t pos = ns > p ? (int64_t)floor(((double)b + u) * (double)ns / (double)p) : b;
+        const int64_t j = sh[pos].j;
+        const double pj[3] = {x[j], y[j], z[j]};
+        double d[3];
+        for (int k = 0; k < 3; ++k) d[k] = min_image(pi_[k] - pj[k], L);
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        double f[3];
+        pair_force(q[i], q[j], eps[i], eps[j], sig[i], sig[j], alpha, d, r2, f);
+        for (int k = 0; k < 3; ++k) rsum_add(&shell[k], f[k]);
+    }
+    for (int k = 0; k < 3; ++k) out[k] = (core[k].s + core[k].c) + wgt * (shell[k].s + shell[k].c);
+    return ns;
+}
+
+static int valid(double L, double rc, double rs, int32_t p) { return rc > 0.0 && rc <= rs && rs < 0.5 * L && p >= 1; }
+
+/*
  * RBL short-range force (Algorithm 2).  u: N uniforms in [0, 1) (the batch offsets).
  * F: 3N doubles, F[d N + i].  ns_out (may be NULL): N_s of every particle.
  * Returns 0, or -1 for invalid cutoffs (need 0 < r_c <= r_s < L/2, p >= 1).
@@ -115,57 +166,23 @@ static int cmp_entry(const void *a, const void *b) {
 int oracle_rbl_short_force(int64_t n, const double *x, const double *y, const double *z, const double *q,
                            const double *eps, const double *sig, double L, double alpha, double rc, double rs,
                            int32_t p, const double *u, double *F, int64_t *ns_out) {
-    if (!(rc > 0.0 && rc <= rs && rs < 0.5 * L) || p < 1) return -1;
+    if (!valid(L, rc, rs, p)) return -1;
     const grid g = make_grid(L, rc, rs);
-    const double rc2 = rc * rc, rs2 = rs * rs;
     double *raw = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
     int bad = (raw == NULL);
-#pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t i = 0; i < n; ++i) {
-        if (bad) continue;
-        const double pi_[3] = {x[i], y[i], z[i]};
-        const int64_t ci[3] = {cell_of(x[i], L, g.nc), cell_of(y[i], L, g.nc), cell_of(z[i], L, g.nc)};
-        rsum core[3] = {{0, 0}, {0, 0}, {0, 0}};
+#pragma omp parallel
+    {
         shell_entry *sh = (shell_entry *)malloc(sizeof(shell_entry) * (size_t)(n > 0 ? n : 1));
-        if (sh == NULL) { bad = 1; continue; }
-        int64_t ns = 0;
-        for (int64_t j = 0; j < n; ++j) {
-            if (j == i) continue;
-            const double pj[3] = {x[j], y[j], z[j]};
-            double d[3];
-            for (int k = 0; k < 3; ++k) d[k] = min_image(pi_[k] - pj[k], L);
-            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-            if (r2 < rc2) {
-                double f[3];
-                pair_force(q[i], q[j], eps[i], eps[j], sig[i], sig[j], alpha, d, r2, f);
-                for (int k = 0; k < 3; ++k) rsum_add(&core[k], f[k]);
-            } else if (r2 <= rs2) {
-                const int64_t cj[3] = {cell_of(x[j], L, g.nc), cell_of(y[j], L, g.nc), cell_of(z[j], L, g.nc)};
-                const int64_t s = (stencil_pos(ci[0], cj[0], &g) * g.span + stencil_pos(ci[1], cj[1], &g)) * g.span +
-                                  stencil_pos(ci[2], cj[2], &g);
-                sh[ns].key = s * n + j;
-                sh[ns].j = j;
-                ++ns;
-            }
-        }
-        qsort(sh, (size_t)ns, sizeof(shell_entry), cmp_entry);
-        rsum shell[3] = {{0, 0}, {0, 0}, {0, 0}};
-        const double wgt = ns > p ? (double)ns / (double)p : 1.0;
-        const int64_t nb = ns > p ? p : ns;
-        for (int64_t b = 0; b < nb; ++b) {
-            const int64_t pos = ns > p ? (int64_t)floor(((double)b + u[i]) * (double)ns / (double)p) : b;
-            const int64_t j = sh[pos].j;
-            double d[3];
-            for (int k = 0; k < 3; ++k) d[k] = min_image(pi_[k] - (k == 0 ? x[j] : k == 1 ? y[j] : z[j]), L);
-            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (sh == NULL) bad = 1;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n; ++i) {
+            if (bad) continue;
             double f[3];
-            pair_force(q[i], q[j], eps[i], eps[j], sig[i], sig[j], alpha, d, r2, f);
-            for (int k = 0; k < 3; ++k) rsum_add(&shell[k], f[k]);
+            const int64_t ns = rbl_raw_one(i, n, x, y, z, q, eps, sig, L, alpha, rc * rc, rs * rs, p, u[i], &g, sh, f);
+            for (int k = 0; k < 3; ++k) raw[k * n + i] = f[k];
+            if (ns_out) ns_out[i] = ns;
         }
         free(sh);
-        for (int k = 0; k < 3; ++k)
-            raw[k * n + i] = (core[k].s + core[k].c) + wgt * (shell[k].s + shell[k].c);
-        if (ns_out) ns_out[i] = ns;
     }
     if (bad) { free(raw); return -2; }
     /* F^corr = -(1/N) sum_i (F^core_i + F^shell*_i), index order */
@@ -177,6 +194,35 @@ int oracle_rbl_short_force(int64_t n, const double *x, const double *y, const do
     }
     free(raw);
     return 0;
+}
+
+/*
+ * Raw forces F_i^core + F_i^shell* (no momentum correction) of the selected particles
+ * sel[0..m-1], each by brute force over all n particles; u: their batch offsets (m).
+ * out: 3m doubles, out[d m + s]; ns_out (may be NULL): their N_s.  Returns 0 or -1.
+ */
+int oracle_rbl_raw_subset(int64_t n, const double *x, const double *y, const double *z, const double *q,
+                          const double *eps, const double *sig, double L, double alpha, double rc, double rs,
+                          int32_t p, int64_t m, const int64_t *sel, const double *u, double *out, int64_t *ns_out) {
+    if (!valid(L, rc, rs, p)) return -1;
+    const grid g = make_grid(L, rc, rs);
+    int bad = 0;
+#pragma omp parallel
+    {
+        shell_entry *sh = (shell_entry *)malloc(sizeof(shell_entry) * (size_t)(n > 0 ? n : 1));
+        if (sh == NULL) bad = 1;
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t s = 0; s < m; ++s) {
+            if (bad) continue;
+            double f[3];
+            const int64_t ns = rbl_raw_one(sel[s], n, x, y, z, q, eps, sig, L, alpha, rc * rc, rs * rs, p, u[s], &g,
+                                           sh, f);
+            for (int k = 0; k < 3; ++k) out[k * m + s] = f[k];
+            if (ns_out) ns_out[s] = ns;
+        }
+        free(sh);
+    }
+    return bad ? -2 : 0;
 }
 
 /*

@@ -19,7 +19,7 @@ RBE_FP64, RBE_FP32_MIXED, RBE_FP32 = 0, 1, 2
 RBE_PHASE_AUTO, RBE_PHASE_RECOMPUTE, RBE_PHASE_CACHED = 0, 1, 2
 RBE_SAMPLER_EXACT, RBE_SAMPLER_METROPOLIS = 0, 1
 
-# name -> (restype, argtypes); every symbol that include/rbe.h declares
+# name -> (restype, argtypes); every symbol that include/rbe.h and include/rbl.h declare
 _VP, _I32, _U64, _D, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t
 _ST = ctypes.c_int
 SIGNATURES = {
@@ -52,11 +52,22 @@ SIGNATURES = {
     "rbe_graph_create": (_ST, [_VP, _U64, _U64] + [_VP] * 12),
     "rbe_graph_launch": (_ST, [_VP, _VP]),
     "rbe_graph_destroy": (None, [_VP]),
+    "rbl_plan_create": (_ST, [_VP, _VP]),
+    "rbl_plan_workspace_bytes": (_SZ, [_VP]),
+    "rbl_plan_grid": (_ST, [_VP, _VP, _VP, _VP]),
+    "rbl_plan_destroy": (None, [_VP]),
+    "rbl_short_force": (_ST, [_VP] * 7 + [_U64, _U64] + [_VP] * 4),
     "rbe_status_string": (ctypes.c_char_p, [_ST]),
     "rbe_last_error": (ctypes.c_char_p, []),
     "rbe_abi_version": (_I32, []),
 }
 
+
+
+class RBLParams(ctypes.Structure):
+    """rbl_params: N, L, alpha, r_c, r_s, p."""
+    _fields_ = [("N", ctypes.c_int64), ("L", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("r_c", ctypes.c_double), ("r_s", ctypes.c_double), ("p", ctypes.c_int32)]
 
 
 class BatchDesc(ctypes.Structure):

@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librbe.so")
-SOURCES = ["rbe_host.cpp", "rbe_kernels.hip"]
+SOURCES = ["rbe_host.cpp", "rbe_kernels.hip", "rbl_kernels.hip"]
 ARCH = "gfx950"
 
 

@@ -19,9 +19,10 @@
 #include "rbe_internal.h"
 
 namespace rbe {
-namespace {
 
+namespace {
 thread_local std::string g_last_error;
+}  // namespace
 
 rbe_status fail(rbe_status st, const char* fmt, ...) {
   char buf[512];
@@ -47,6 +48,8 @@ rbe_status device_ok() {
     return fail(RBE_ENODEV, "no HIP device available (%s)", hipGetErrorString(err));
   return RBE_OK;
 }
+
+namespace {
 
 constexpr size_t kAlign = 256;
 constexpr double kTwoPi = 6.283185307179586476925286766559;

@@ -129,6 +129,13 @@ struct LaunchShape {
   hipEvent_t ev_rho_begin, ev_rho_end, ev_force_begin, ev_force_end;
 };
 
+// Error reporting shared by the library's entry points (rbe_host.cpp): fail() records the
+// message returned by rbe_last_error() and returns st; hip_fail() wraps a HIP error;
+// device_ok() reports RBE_ENODEV when no device is present.
+rbe_status fail(rbe_status st, const char* fmt, ...);
+rbe_status hip_fail(hipError_t e, const char* what);
+rbe_status device_ok();
+
 // Kernel launchers (rbe_kernels.hip).  Each returns hipSuccess or the launch error.
 // launch_rho with rows != 0 (FP32 forms) also writes the force rows from the reduced rho (wk:
 // the weights); launch_force with rows_ready != 0 uses them, otherwise it writes them from

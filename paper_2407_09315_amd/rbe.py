@@ -449,3 +449,67 @@ class EvalGraph:
 
     def __del__(self):
         self.close()
+
+
+# ---------------------------------------------------------------------- RBL short-range force
+
+def rbl_short_force(plan, x, y, z, q, eps, sig, seed, step, F, ns, ws, stream=None):
+    check(load().rbl_short_force(plan, _ptr(x), _ptr(y), _ptr(z), _ptr(q), _ptr(eps), _ptr(sig), int(seed),
+                                 int(step), _ptr(F), _ptr(ns), _ptr(ws), _stream(stream)), "rbl_short_force")
+
+
+class RBLPlan:
+    """A random batch list plan (rbl_plan_create) and its device workspace."""
+
+    def __init__(self, n: int, L: float, alpha: float, r_c: float, r_s: float, p: int, device=None):
+        self.lib = load()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.n = int(n)
+        prm = _lib.RBLParams(int(n), float(L), float(alpha), float(r_c), float(r_s), int(p))
+        handle = ctypes.c_void_p()
+        check(self.lib.rbl_plan_create(ctypes.byref(prm), ctypes.byref(handle)), "rbl_plan_create")
+        self.handle = handle
+        _live_plans.add(self)
+        nbytes = int(self.lib.rbl_plan_workspace_bytes(self.handle))
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._raw = raw
+        self.ws = raw[off:off + nbytes]
+
+    def grid(self):
+        v = [ctypes.c_int32() for _ in range(3)]
+        check(self.lib.rbl_plan_grid(self.handle, *[ctypes.byref(a) for a in v]), "rbl_plan_grid")
+        return tuple(a.value for a in v)
+
+    def short_force(self, x, y, z, q, eps, sig, seed: int, step: int, F=None, ns=None, stream=None):
+        """(F (3, N) FP64, N_s (N,) int32) for one evaluation; enqueued without synchronisation."""
+        for name, t in (("x", x), ("y", y), ("z", z), ("q", q), ("eps", eps), ("sig", sig)):
+            _dev(t, torch.float64, name)
+            if t.numel() != self.n:
+                raise ValueError(f"{name} has {t.numel()} elements, the plan {self.n}")
+        if F is None:
+            F = torch.empty((3, self.n), dtype=torch.float64, device=self.device)
+        if ns is None:
+            ns = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        _dev(F, torch.float64, "F")
+        _dev(ns, torch.int32, "ns")
+        rbl_short_force(self.handle, x, y, z, q, eps, sig, seed, step, F, ns, self.ws, stream)
+        return F, ns
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and not _released_all:
+            self.lib.rbl_plan_destroy(h)
+        self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

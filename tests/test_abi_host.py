@@ -21,10 +21,14 @@ from paper_2407_09315_amd import _lib, rbe
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
+def _headers():
+    return "".join(open(os.path.join(ROOT, "include", h)).read() for h in ("rbe.h", "rbl.h"))
+
+
 def _declared_functions():
-    src = open(os.path.join(ROOT, "include", "rbe.h")).read()
+    src = _headers()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(rbe_[a-z0-9_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(rb[el]_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -42,11 +46,11 @@ _CTYPE_OF = {"int32_t": ctypes.c_int32, "uint64_t": ctypes.c_uint64, "double": c
 
 
 def _prototypes():
-    """name -> (return C type, [parameter C types]) of every function rbe.h declares."""
-    src = open(os.path.join(ROOT, "include", "rbe.h")).read()
+    """name -> (return C type, [parameter C types]) of every function rbe.h and rbl.h declare."""
+    src = _headers()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     out = {}
-    for ret, name, params in re.findall(r"([A-Za-z_][\w \*]*?)\b(rbe_[a-z0-9_]+)\s*\(([^)]*)\)\s*;", src):
+    for ret, name, params in re.findall(r"([A-Za-z_][\w \*]*?)\b(rb[el]_[a-z0-9_]+)\s*\(([^)]*)\)\s*;", src):
         ps = [p.strip() for p in params.split(",") if p.strip() and p.strip() != "void"]
         out[name] = (ret.strip(), ps)
     return out
@@ -234,3 +238,37 @@ def test_metropolis_argument_checks():
     assert lib.rbe_plan_set_sampler(h, _lib.RBE_SAMPLER_METROPOLIS, 16) == 0
     assert lib.rbe_plan_set_sampler(None, 0, 0) == _lib.RBE_EINVAL
     lib.rbe_plan_destroy(h)
+
+
+def _rbl(N=1000, L=40.0, alpha=0.1, rc=5.0, rs=10.0, p=10):
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    prm = _lib.RBLParams(N, L, alpha, rc, rs, p)
+    return lib.rbl_plan_create(ctypes.byref(prm), ctypes.byref(h)), h
+
+
+def test_rbl_plan_validation_and_grid():
+    lib = _lib.load()
+    st, h = _rbl()
+    assert st == 0 and h.value
+    v = [ctypes.c_int32() for _ in range(3)]
+    assert lib.rbl_plan_grid(h, *[ctypes.byref(a) for a in v]) == 0
+    nc, R, span = (a.value for a in v)
+    assert (nc, R, span) == (8, 2, 5)                    # h = 5 = r_c, reach ceil(10 / 5)
+    assert lib.rbl_plan_workspace_bytes(h) % 256 == 0
+    lib.rbl_plan_destroy(h)
+    st, h = _rbl(L=21.0, rc=5.0, rs=10.0)                # 4 cells per axis: the stencil wraps
+    assert st == 0
+    assert lib.rbl_plan_grid(h, *[ctypes.byref(a) for a in v]) == 0
+    assert (v[0].value, v[2].value) == (4, 4)
+    lib.rbl_plan_destroy(h)
+    for bad in (dict(rs=20.0), dict(rc=0.0), dict(rc=11.0), dict(p=0), dict(N=-1), dict(alpha=-1.0),
+                dict(L=float("nan"))):
+        st, h = _rbl(**bad)
+        assert st == _lib.RBE_EINVAL and not h.value, bad
+    st, h = _rbl()
+    assert lib.rbl_short_force(h, *([None] * 6), 1, 0, None, None, None, None) == _lib.RBE_EWORKSPACE
+    if not torch.cuda.is_available():
+        assert lib.rbl_short_force(h, *([ctypes.c_void_p(256)] * 6), 1, 0, ctypes.c_void_p(256), None,
+                                   ctypes.c_void_p(256), None) == _lib.RBE_ENODEV
+    lib.rbl_plan_destroy(h)

@@ -1,0 +1,97 @@
+"""GPU parity of the random batch list (RBL) short-range force against the FP64 oracle.
+
+  * whole systems (every force, every N_s) on the same batch offsets: the primitive
+    electrolyte at the paper's density with p = 30 and 100, unequal LJ parameters, a
+    particle count off the block size, a box whose stencil wraps, and a batch larger than
+    every shell (the exact truncated force);
+  * the 1M-particle benchmark system: N_s exact and the raw force differences F_i - F_0 of
+    sampled particles (the momentum correction is one vector for all) against the oracle's
+    brute-force raw forces of those particles, and sum_i F_i = 0;
+  * repeated calls are bitwise equal, and a new step gives a new batch.
+Bounds: FP64 element-wise, max_i |dF_i| / RMS |F| < 1e-11 and relative RMS < 1e-12; N_s
+bit-exact (it is integer work).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import rbe_inputs as ri
+from paper_2407_09315_amd import RBLPlan
+from parity_util import dev, force_err, max_err, note, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(s, alpha, rc, rs, p, seed, step):
+    plan = RBLPlan(s.n, s.L, alpha, rc, rs, p, device=dev())
+    X = [to_dev(a) for a in (s.x, s.y, s.z, s.q, s.eps, s.sig)]
+    F, ns = plan.short_force(*X, seed=seed, step=step)
+    torch.cuda.synchronize()
+    return plan, X, F.cpu().numpy(), ns.cpu().numpy()
+
+
+CASES = [
+    # (n, density, alpha, rc, rs, p, unequal LJ)
+    (2000, 0.01, 0.06, 6.0, 12.0, 30, False),
+    (2000, 0.01, 0.06, 6.0, 12.0, 100, False),
+    (4099, 0.01, 0.1, 5.0, 11.0, 17, True),
+    (250, 0.01, 0.06, 6.0, 12.0, 30, False),     # L = 29.2: 4 cells per axis, the stencil wraps
+    (1500, 0.01, 0.06, 6.0, 12.0, 4000, False),  # batch larger than every shell: exact force
+    (2500, 0.3, 0.3, 2.5, 5.0, 10, True),        # denser: about 5 particles per cell
+]
+
+
+@pytest.mark.parametrize("n,density,alpha,rc,rs,p,unequal", CASES)
+def test_rbl_parity(n, density, alpha, rc, rs, p, unequal):
+    s = ri.primitive_electrolyte(n, density, 300 + n)
+    if unequal:
+        g = np.random.default_rng(n)
+        s.eps = g.uniform(0.5, 1.5, n)
+        s.sig = g.uniform(0.8, 1.3, n)
+    seed, step = 77, 3
+    note(f"case rbl n={n} L={s.L:.2f} rc={rc} rs={rs} p={p}")
+    plan, X, F, ns = _run(s, alpha, rc, rs, p, seed, step)
+    note(f"  grid {plan.grid()}")
+    F_ref, ns_ref = oracle.rbl_short_force(s.x, s.y, s.z, s.q, s.eps, s.sig, s.L, alpha, rc, rs, p,
+                                           oracle.rbl_offsets(seed, step, n))
+    assert np.array_equal(ns, ns_ref)
+    ef, em = force_err(F, F_ref), max_err(F, F_ref)
+    note(f"  force rel RMS {ef:.2e}, max {em:.2e}, mean N_s {ns.mean():.1f}")
+    assert ef < 1e-12 and em < 1e-11
+    assert np.all(np.abs(F.sum(axis=1)) < 1e-11 * np.abs(F).sum(axis=1))
+    plan.close()
+
+
+def test_rbl_repeatable_and_step_dependent():
+    s = ri.primitive_electrolyte(3000, 0.01, 12)
+    plan = RBLPlan(s.n, s.L, 0.06, 6.0, 12.0, 30, device=dev())
+    X = [to_dev(a) for a in (s.x, s.y, s.z, s.q, s.eps, s.sig)]
+    F1, n1 = plan.short_force(*X, seed=5, step=0)
+    F2, n2 = plan.short_force(*X, seed=5, step=0)
+    F3, _ = plan.short_force(*X, seed=5, step=1)
+    torch.cuda.synchronize()
+    assert torch.equal(F1, F2) and torch.equal(n1, n2)
+    assert not torch.equal(F1, F3)
+    plan.close()
+
+
+def test_rbl_1M_sampled():
+    """The benchmark system (1M particles, rc = 6, rs = 12, p = 30): N_s and raw force
+    differences of 200 sampled particles against the oracle, and zero total force."""
+    s = ri.primitive_electrolyte(1_000_000, 0.01, 1006)
+    alpha, rc, rs, p, seed, step = 0.06, 6.0, 12.0, 30, 9, 4
+    note(f"case rbl 1M L={s.L:.2f}")
+    plan, X, F, ns = _run(s, alpha, rc, rs, p, seed, step)
+    sel = np.concatenate([[0], np.sort(np.random.default_rng(2).choice(np.arange(1, s.n), 199, replace=False))])
+    raw, ns_ref = oracle.rbl_raw_subset(s.x, s.y, s.z, s.q, s.eps, s.sig, s.L, alpha, rc, rs, p, sel,
+                                        oracle.rbl_offsets(seed, step, sel))
+    assert np.array_equal(ns[sel], ns_ref)
+    d_gpu = F[:, sel] - F[:, sel[:1]]
+    d_ref = raw - raw[:, :1]
+    rms = np.sqrt(np.mean(np.sum(raw ** 2, axis=0)))
+    err = np.max(np.sqrt(np.sum((d_gpu - d_ref) ** 2, axis=0))) / rms
+    note(f"  max |d(F_i - F_0)| / RMS {err:.2e}, mean N_s {ns.mean():.1f}")
+    assert err < 1e-11
+    assert np.all(np.abs(F.sum(axis=1)) < 1e-10 * np.abs(F).sum(axis=1))
+    plan.close()
