@@ -182,6 +182,8 @@ def main():
         log("batched done")
         extra.update(bench_virial(torch, Plan, Batch, X, s, alpha, P, args.steps))
         log("virial done")
+        extra.update(bench_rbl(torch, ri, dev, max(5, args.steps // 5)))
+        log("rbl done")
 
     f32, f64 = res["fp32"], res["fp64"]
     value = terms / f32["wall_s"] / 1e9
@@ -396,6 +398,32 @@ def errors_10M(torch, ri, Plan, Batch, dev):
                      "rho_max_over_qnorm": float(np.max(np.abs(rc - rho_ref)) / np.sqrt(np.sum(s.q ** 2)))}
         plan.close()
         del F, U, rho
+    return out
+
+
+def bench_rbl(torch, ri, dev, steps):
+    """RBL short-range force (cell list, core sum, shell batch, momentum correction) on the
+    paper's primitive electrolyte at 0.01 particles / sigma^3, 1M particles, r_c = 6, r_s = 12,
+    alpha = 0.06, p = 30 and 100: whole evaluations back to back."""
+    from paper_2407_09315_amd import RBLPlan
+    s = ri.primitive_electrolyte(1_000_000, 0.01, 1006)
+    X = [torch.tensor(a, dtype=torch.float64, device=dev) for a in (s.x, s.y, s.z, s.q, s.eps, s.sig)]
+    out = {}
+    for p in (30, 100):
+        plan = RBLPlan(s.n, s.L, 0.06, 6.0, 12.0, p, device=dev)
+        F, ns = plan.short_force(*X, seed=1, step=0)
+        for k in range(3):
+            plan.short_force(*X, seed=1, step=k, F=F, ns=ns)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            plan.short_force(*X, seed=1, step=k, F=F, ns=ns)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[f"rbl_short_force_electrolyte_1M_p{p}"] = {
+            "ms_per_evaluation": round(dt * 1e3, 4), "N": s.n, "L": round(s.L, 4), "r_c": 6.0, "r_s": 12.0, "p": p,
+            "mean_shell_size": round(float(ns.double().mean()), 2), "grid": plan.grid()}
+        plan.close()
     return out
 
 

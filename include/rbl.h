@@ -19,7 +19,8 @@
  * The batch (the paper fixes no scheme): systematic sampling of the shell in a fixed
  * traversal order.  Particle i draws u_i in [0, 1) -- word 0 of Philox4x64-10 (Salmon
  * et al., SC'11) with key (seed, step) and counter (i, 0, 3, 0), top 53 bits -- and
- * takes the shell members at positions floor((b + u_i) N_s / p), b = 0..p-1, each with
+ * takes the shell members at positions min(floor((b + u_i) N_s / p), N_s - 1), b = 0..p-1
+ * (the minimum is the exact value where the rounding of b + u_i reaches p), each with
  * weight N_s / p; when N_s <= p the batch is the whole shell with weight 1.  Every
  * shell particle is in the batch with probability p / N_s, so the estimate is unbiased.
  * Traversal order: cells of side h = L / nc, nc = floor(L / r_c); stencil reach
@@ -31,6 +32,12 @@
  * F[d N + i]; all arithmetic is FP64.  Scratch lives in a caller workspace of
  * rbl_plan_workspace_bytes() bytes, 256-byte aligned; work is enqueued on `stream`
  * without synchronisation.  Results are bitwise reproducible for the same inputs.
+ *
+ * Work split: the fast path holds a cell's stencil of up to `stencil_positions` particles
+ * in on-chip memory and up to `pairs_per_particle` core and batch pairs per particle in the
+ * workspace (rbl_plan_capacity; sized from the mean density N / L^3 with a wide Poisson
+ * allowance).  Particles beyond either take a slower path with the same result; the sum
+ * order of a particle's pairs differs between the two, by rounding only.
  */
 #ifndef RBL_H
 #define RBL_H
@@ -58,6 +65,8 @@ rbe_status rbl_plan_create(const rbl_params *params, rbl_plan **out);
 size_t rbl_plan_workspace_bytes(const rbl_plan *plan);
 /* The cell grid: cells per axis, stencil reach R (in cells) and cells per stencil axis. */
 rbe_status rbl_plan_grid(const rbl_plan *plan, int32_t *cells_per_axis, int32_t *reach, int32_t *stencil_span);
+/* The fast path's limits: pair slots per particle and stencil positions per cell. */
+rbe_status rbl_plan_capacity(const rbl_plan *plan, int32_t *pairs_per_particle, int32_t *stencil_positions);
 void rbl_plan_destroy(rbl_plan *plan);
 
 /*

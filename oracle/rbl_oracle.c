@@ -142,7 +142,10 @@ static int64_t rbl_raw_one(int64_t i, int64_t n, const double *x, const double *
     const double wgt = ns > p ? (double)ns / (double)p : 1.0;
     const int64_t nb = ns > p ? p : ns;
     for (int64_t b = 0; b < nb; ++b) {
-        const int64_t pos = ns > p ? (int64_t)floor(((double)b + u) * (double)ns / (double)p) : b;
+        int64_t pos = ns > p ? (int64_t)floor(((double)b + u) * (double)ns / (double)p) : b;
+        /* b + u < p, so the exact position is at most N_s - 1; the rounding of b + u can
+           reach p, and the clamp restores the exact value there */
+        if (pos > ns - 1) pos = ns - 1;
         const int64_t j = sh[pos].j;
         const double pj[3] = {x[j], y[j], z[j]};
         double d[3];

@@ -6,13 +6,16 @@
 //   cells   : cell of every particle, per-cell counts (atomic adds), exclusive scan into
 //             cell starts, scatter into cell order (atomic slots), then every cell's short
 //             segment sorted by particle index, so the order is deterministic;
-//   gather  : positions, charges and LJ parameters copied into cell order;
-//   force   : one thread per particle in cell order (neighbouring lanes share most of their
-//             stencil cells); pass 1 over the stencil sums the core and counts the shell,
-//             pass 2 walks the shell again and adds the batch members, stopping after the
-//             last one; the raw forces are written by particle index and summed per block
-//             in a fixed order;
-//   correct : one block adds the block sums in order; every force gets -(1/N) of the total.
+//   gather  : positions, charges and LJ parameters copied into cell order, and every
+//             particle's batch offset u_i drawn;
+//   select  : one wave per cell classifies the cell's stencil against its particles (core
+//             and shell ballot masks) and writes every particle's pairs -- the core and the
+//             batch -- into a slot of Q entries;
+//   pairs   : one lane per particle adds its slot's pair forces in order;
+//   fallback: particles whose stencil or pair count exceeds what the selection holds are
+//             done one wave each, classifying the stencil window by window;
+//   correct : two fixed-order summations of the forces; every force gets -(1/N) of the
+//             total.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,15 +48,18 @@ struct RblWs {
   int32_t* fill;
   int32_t* start;    // ncell + 1
   int32_t* bsum;     // scan block sums
-  int32_t* cell;     // N
+  int32_t* cell;     // N, by particle index
   int32_t* idx;      // N: particle index at each cell-order position
-  double* xs;        // N each, in cell order
-  double* ys;
-  double* zs;
-  double* qs;
-  double* es;
-  double* ss;
-  double* partial;   // 3 per force block
+  double4* pq;       // N, in cell order: x, y, z, q
+  double2* lj;       // N, in cell order: sqrt(eps), sig
+  int2* range;       // ncell: first and one-past-last cell-order position of each cell
+  double* ru;        // N, in cell order: the particle's batch offset u_i
+  uint32_t* slot;    // N x Q pair entries, in cell order
+  int32_t* cnt;      // N, in cell order: pairs in the slot, -1 for the fallback
+  int32_t* tns;      // N, in cell order: N_s
+  int32_t* fb;       // N: cell-order positions left to the fallback
+  int32_t* nfb;      // 1: their count
+  double* partial;   // 3 per block of the first summation
   double* corr;      // 3
 };
 
@@ -132,7 +138,8 @@ __global__ __launch_bounds__(kRblBlock) void rbl_scan_offsets_kernel(int32_t* __
 
 __global__ __launch_bounds__(kRblBlock) void rbl_scan_apply_kernel(const int32_t* __restrict__ count, int64_t ncell,
                                                                    const int32_t* __restrict__ bsum,
-                                                                   int32_t* __restrict__ start, int64_t n) {
+                                                                   int32_t* __restrict__ start, int2* __restrict__ range,
+                                                                   int64_t n) {
   __shared__ int32_t sh[kRblBlock];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
   int32_t off = bsum[blockIdx.x];
@@ -141,7 +148,10 @@ __global__ __launch_bounds__(kRblBlock) void rbl_scan_apply_kernel(const int32_t
     const int32_t v = c < ncell ? count[c] : 0;
     int32_t tot;
     const int32_t ex = block_exclusive_scan(v, sh, &tot);
-    if (c < ncell) start[c] = off + ex;
+    if (c < ncell) {
+      start[c] = off + ex;
+      range[c] = make_int2(off + ex, off + ex + v);
+    }
     off += tot;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) start[ncell] = (int32_t)n;
@@ -177,25 +187,27 @@ __global__ __launch_bounds__(kRblBlock) void rbl_segment_sort_kernel(const int32
 __global__ __launch_bounds__(kRblBlock) void rbl_gather_kernel(const double* __restrict__ x, const double* __restrict__ y,
                                                                const double* __restrict__ z, const double* __restrict__ q,
                                                                const double* __restrict__ eps,
-                                                               const double* __restrict__ sig, int64_t n, RblWs w) {
+                                                               const double* __restrict__ sig, int64_t n, uint64_t seed,
+                                                               uint64_t step, RblWs w) {
   const int64_t t = (int64_t)blockIdx.x * kRblBlock + threadIdx.x;
   if (t >= n) return;
   const int32_t i = w.idx[t];
-  w.xs[t] = x[i];
-  w.ys[t] = y[i];
-  w.zs[t] = z[i];
-  w.qs[t] = q[i];
-  w.es[t] = eps[i];
-  w.ss[t] = sig[i];
+  w.pq[t] = make_double4(x[i], y[i], z[i], q[i]);
+  w.lj[t] = make_double2(sqrt(eps[i]), sig[i]);
+  U64x4 ctr = {{(uint64_t)i, 0ull, 3ull, 0ull}};
+  w.ru[t] = u01_53(philox4x64_10(ctr, seed, step).v[0]);
 }
 
-// Minimum-image difference a - b of one coordinate: d - L rint(d / L).  Evaluated without
-// contraction into FMAs, so the squared distance that decides core, shell or neither is
-// the same IEEE expression on every side.
-__device__ inline double min_image_diff(double a, double b, double L) {
+// Minimum-image difference a - b of one coordinate: d - L rint(d / L), with d / L taken as
+// d (1 / L).  The two can differ by one rounding, which changes rint only when |d| is
+// within a rounding of L / 2, beyond every cutoff (r_s < L / 2); the result is then the
+// other image of the same magnitude.  Evaluated without contraction into FMAs, so the
+// squared distance that decides core, shell or neither is the same IEEE expression on
+// every side.
+__device__ inline double min_image_diff(double a, double b, double L, double invL) {
 #pragma clang fp contract(off)
   const double d = a - b;
-  return d - L * rint(d / L);
+  return d - L * rint(d * invL);
 }
 
 __device__ inline double dist2(double dx, double dy, double dz) {
@@ -203,22 +215,25 @@ __device__ inline double dist2(double dx, double dy, double dz) {
   return dx * dx + dy * dy + dz * dz;
 }
 
-// Force on i from j given d = r_i - r_j and r2 = |d|^2, added into f (Eqs. lj and fshort).
-__device__ inline void pair_force_add(double qi, double qj, double ei, double ej, double si, double sj,
+// Force on i from j given d = r_i - r_j and r2 = |d|^2, added into f (Eqs. lj and fshort),
+// with the mixed LJ well depth as sqrt(eps_i) sqrt(eps_j) and one division, 1 / r^2.
+__device__ inline void pair_force_add(double qi, double qj, double rei, double rej, double si, double sj,
                                       double alpha, double sqa, double tsap, double dx, double dy, double dz,
                                       double r2, double& fx, double& fy, double& fz) {
+  const double ir2 = 1.0 / r2;
   const double r = sqrt(r2);
+  const double ir = r * ir2;
   double g = 0.0;
-  const double e = sqrt(ei * ej);
+  const double e = rei * rej;
   if (e != 0.0) {
     const double s = 0.5 * (si + sj);
-    const double s2 = s * s / r2;
+    const double s2 = s * s * ir2;
     const double s6 = s2 * s2 * s2;
-    g += 24.0 * e * (2.0 * s6 * s6 - s6) / r2;
+    g += 24.0 * e * (2.0 * s6 * s6 - s6) * ir2;
   }
   if (qi != 0.0 && qj != 0.0) {
-    const double kern = erfc(sqa * r) / r2 + tsap * exp(-alpha * r2) / r;
-    g += qi * qj * kern / r;
+    const double kern = erfc(sqa * r) * ir2 + tsap * exp(-alpha * r2) * ir;
+    g += qi * qj * kern * ir;
   }
   fx += g * dx;
   fy += g * dy;
@@ -230,115 +245,403 @@ __device__ inline int32_t wrap_cell(int32_t c, int32_t nc) {
   return m < 0 ? m + nc : m;
 }
 
-__global__ __launch_bounds__(kRblBlock) void rbl_force_kernel(RblWs w, int64_t n, double L, double alpha, double sqa,
-                                                              double tsap, double rc2, double rs2, int32_t p,
-                                                              RblGrid g, uint64_t seed, uint64_t step,
-                                                              double* __restrict__ F, int32_t* __restrict__ ns_out) {
-  __shared__ double red[3][kRblBlock];
-  const int64_t t = (int64_t)blockIdx.x * kRblBlock + threadIdx.x;
-  double fx = 0.0, fy = 0.0, fz = 0.0;
-  if (t < n) {
-    const int32_t i = w.idx[t];
-    const double xi = w.xs[t], yi = w.ys[t], zi = w.zs[t];
-    const double qi = w.qs[t], ei = w.es[t], si = w.ss[t];
-    const int32_t nc = g.nc;
-    const int32_t cx = cell_coord(xi, L, nc), cy = cell_coord(yi, L, nc), cz = cell_coord(zi, L, nc);
-    const int32_t o0 = g.wrap ? 0 : -g.R;
-    // pass 1: core sum and shell count
-    double cfx = 0.0, cfy = 0.0, cfz = 0.0;
-    int32_t ns = 0;
-    for (int32_t a = 0; a < g.span; ++a) {
-      const int32_t ca = wrap_cell(cx + o0 + a, nc);
-      for (int32_t b = 0; b < g.span; ++b) {
-        const int32_t cb = wrap_cell(cy + o0 + b, nc);
-        for (int32_t c = 0; c < g.span; ++c) {
-          const int32_t cell = (ca * nc + cb) * nc + wrap_cell(cz + o0 + c, nc);
-          const int32_t e = w.start[cell + 1];
-          for (int32_t u = w.start[cell]; u < e; ++u) {
-            const double dx = min_image_diff(xi, w.xs[u], L);
-            const double dy = min_image_diff(yi, w.ys[u], L);
-            const double dz = min_image_diff(zi, w.zs[u], L);
-            const double r2 = dist2(dx, dy, dz);
-            if (r2 < rc2) {
-              if (w.idx[u] != i)
-                pair_force_add(qi, w.qs[u], ei, w.es[u], si, w.ss[u], alpha, sqa, tsap, dx, dy, dz, r2, cfx, cfy,
-                               cfz);
-            } else if (r2 <= rs2) {
-              ++ns;
-            }
-          }
-        }
-      }
-    }
-    // pass 2: the shell batch in traversal order
-    double sfx = 0.0, sfy = 0.0, sfz = 0.0;
-    double wgt = 1.0;
-    if (ns > 0) {
-      const bool sub = ns > p;
-      double uoff = 0.0;
-      int64_t target = 0;
-      int32_t picked = 0;
-      if (sub) {
-        U64x4 ctr = {{(uint64_t)i, 0ull, 3ull, 0ull}};
-        uoff = u01_53(philox4x64_10(ctr, seed, step).v[0]);
-        wgt = (double)ns / (double)p;
-        target = (int64_t)floor((0.0 + uoff) * (double)ns / (double)p);
-      }
-      const int32_t want = sub ? p : ns;
-      int64_t k = 0;
-      for (int32_t a = 0; a < g.span && picked < want; ++a) {
-        const int32_t ca = wrap_cell(cx + o0 + a, nc);
-        for (int32_t b = 0; b < g.span && picked < want; ++b) {
-          const int32_t cb = wrap_cell(cy + o0 + b, nc);
-          for (int32_t c = 0; c < g.span && picked < want; ++c) {
-            const int32_t cell = (ca * nc + cb) * nc + wrap_cell(cz + o0 + c, nc);
-            const int32_t e = w.start[cell + 1];
-            for (int32_t u = w.start[cell]; u < e && picked < want; ++u) {
-              const double dx = min_image_diff(xi, w.xs[u], L);
-              const double dy = min_image_diff(yi, w.ys[u], L);
-              const double dz = min_image_diff(zi, w.zs[u], L);
-              const double r2 = dist2(dx, dy, dz);
-              if (r2 < rc2 || r2 > rs2) continue;
-              if (!sub || k == target) {
-                pair_force_add(qi, w.qs[u], ei, w.es[u], si, w.ss[u], alpha, sqa, tsap, dx, dy, dz, r2, sfx, sfy,
-                               sfz);
-                ++picked;
-                if (sub) target = (int64_t)floor(((double)picked + uoff) * (double)ns / (double)p);
-              }
-              ++k;
-            }
-          }
-        }
-      }
-    }
-    fx = cfx + wgt * sfx;
-    fy = cfy + wgt * sfy;
-    fz = cfz + wgt * sfz;
-    F[i] = fx;
-    F[n + i] = fy;
-    F[2 * n + i] = fz;
-    if (ns_out != nullptr) ns_out[i] = ns;
-  }
-  // block sums of the raw forces in a fixed order
-  red[0][threadIdx.x] = fx;
-  red[1][threadIdx.x] = fy;
-  red[2][threadIdx.x] = fz;
-  __syncthreads();
-  for (int s = kRblBlock / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s)
-      for (int d = 0; d < 3; ++d) red[d][threadIdx.x] += red[d][threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x < 3) w.partial[3 * (int64_t)blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+constexpr int kRblWaves = kRblBlock / 64;   // waves per block
+constexpr int kListCap = 1024;              // stencil positions held in LDS per wave
+constexpr int kBatchCap = 256;              // batch positions held in LDS per wave (fallback)
+constexpr int kTgtGroup = 8;                // targets classified together
+constexpr int kMaxChunks = kListCap / 64;
+constexpr int kFallbackBlocks = 512;
+constexpr int kCorrBlocks = 256;
+
+struct RblArgs {
+  int64_t n, ncell;
+  int32_t nblk, nblk8;   // blocks of the select kernel and that count over the 8 XCDs, rounded up
+  int32_t p, Q;          // batch size, pair slots per particle
+  double L, invL, alpha, sqa, tsap, rc2, rs2;
+};
+
+__device__ inline int32_t lanes_below(uint64_t m) {
+  return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// F^corr = -(1/N) sum of the block sums (thread t adds blocks t, t + 256, ... in order, then
-// a fixed tree).
-__global__ __launch_bounds__(kRblBlock) void rbl_corr_kernel(RblWs w, int32_t nblocks, int64_t n) {
+// Position of the j-th (from 0) set bit of m; m holds more than j set bits.
+__device__ inline int32_t select_bit(uint64_t m, int32_t j) {
+  uint32_t v = (uint32_t)m;
+  int32_t pos = 0;
+  const int32_t c32 = __popc(v);
+  if (j >= c32) {
+    j -= c32;
+    v = (uint32_t)(m >> 32);
+    pos = 32;
+  }
+  for (int wdt = 16; wdt >= 1; wdt >>= 1) {
+    const int32_t c = __popc(v & ((1u << wdt) - 1u));
+    if (j >= c) {
+      j -= c;
+      v >>= wdt;
+      pos += wdt;
+    }
+  }
+  return pos;
+}
+
+// LDS written by some lanes of a wave and read by others: keep the accesses in order.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The stencil of cell (cx, cy, cz) in traversal order is span^2 rows (x outer, y inner);
+// along z a row is the cells z0, z0 + 1, ... (mod nc), which in cell order is one run of
+// particles, or two when it wraps.  Writes the positions [W0, W0 + kListCap) of the
+// flattened traversal (cell-order indices) into list and returns its length T.
+__device__ int32_t fill_stencil_window(const RblWs& w, const RblGrid& g, int32_t cx, int32_t cy, int32_t cz,
+                                       int32_t W0, int32_t* list, int32_t lane) {
+  const int32_t nc = g.nc, span = g.span, o0 = g.wrap ? 0 : -g.R;
+  const int32_t z0 = wrap_cell(cz + o0, nc);
+  const int32_t nsr = z0 + span > nc ? 2 : 1;
+  const int32_t nseg = span * span * nsr;
+  int32_t T = 0;
+  for (int32_t s0 = 0; s0 < nseg; s0 += 64) {
+    const int32_t sidx = s0 + lane;
+    int32_t sb = 0, sl = 0;
+    if (sidx < nseg) {
+      const int32_t row = sidx / nsr, piece = sidx - row * nsr;
+      const int32_t a = row / span, b = row - a * span;
+      const int64_t base = ((int64_t)wrap_cell(cx + o0 + a, nc) * nc + wrap_cell(cy + o0 + b, nc)) * nc;
+      const int32_t c0 = piece == 0 ? z0 : 0;
+      const int32_t c1 = piece == 0 ? min(z0 + span, nc) : z0 + span - nc;
+      sb = w.range[base + c0].x;
+      sl = w.range[base + c1 - 1].y - sb;
+    }
+    int32_t incl = sl;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    const int32_t ex = T + incl - sl;
+    const int32_t lo = max(ex, W0), hi = min(ex + sl, W0 + kListCap);
+    for (int32_t f = lo; f < hi; ++f) list[f - W0] = sb + (f - ex);
+    T += __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
+  }
+  return T;
+}
+
+// Shell rank of draw b: floor((b + u) N_s / p), the expression and rounding of the
+// definition, at most N_s - 1 (the exact value when the rounding of b + u reaches p).
+__device__ inline int32_t batch_pos(int32_t b, double u, int32_t ns, int32_t p) {
+  return min((int32_t)floor(((double)b + u) * (double)ns / (double)p), ns - 1);
+}
+
+__device__ inline double separation(double xi, double yi, double zi, const double4& o, double L, double invL,
+                                   double& dx, double& dy, double& dz) {
+  dx = min_image_diff(xi, o.x, L, invL);
+  dy = min_image_diff(yi, o.y, L, invL);
+  dz = min_image_diff(zi, o.z, L, invL);
+  return dist2(dx, dy, dz);
+}
+
+// Selection: one wave per cell.  The lanes stream the cell's stencil (its cell-order
+// positions, in traversal order, held in LDS) 64 candidates at a time.  Pass 1, per group of
+// up to kTgtGroup particles of the cell with each candidate loaded once for the group,
+// classifies every candidate against every target into core and shell ballot masks kept in
+// LDS, with N_s, the core count and the shell members before each chunk.  Then each target
+// writes its pair entries -- cell-order index, top bit set for shell members -- into its
+// slot of Q entries: the core (and the whole shell when N_s <= p) by compaction of the
+// masks, and the batch one draw per lane, its shell rank floor((b + u) N_s / p) found through
+// the per-chunk counts and the set bits of that chunk's shell mask.  A cell whose stencil
+// exceeds kListCap positions, or a target with more than Q pairs, is left to the fallback.
+__global__ __launch_bounds__(kRblBlock) void rbl_select_kernel(RblWs w, RblArgs a, RblGrid g) {
+  __shared__ int32_t list_[kRblWaves][kListCap];
+  __shared__ uint64_t mask_[kRblWaves][kTgtGroup][kMaxChunks][2];
+  __shared__ int32_t pre_[kRblWaves][kTgtGroup][kMaxChunks];
+  __shared__ double tpos_[kRblWaves][kTgtGroup][3];
+  __shared__ int32_t nsg_[kRblWaves][kTgtGroup];
+  __shared__ int32_t ncg_[kRblWaves][kTgtGroup];
+  // blocks are dealt to the XCDs in turn: give each XCD a contiguous run of cells
+  const int32_t blk = (int32_t)(blockIdx.x & 7) * a.nblk8 + (int32_t)(blockIdx.x >> 3);
+  if (blk >= a.nblk) return;
+  const int32_t lane = (int32_t)(threadIdx.x & 63);
+  const int32_t wv = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+  const int64_t cidx = (int64_t)blk * kRblWaves + wv;
+  if (cidx >= a.ncell) return;
+  const int2 own = w.range[cidx];
+  const int32_t t0 = __builtin_amdgcn_readfirstlane(own.x), t1 = __builtin_amdgcn_readfirstlane(own.y);
+  if (t1 <= t0) return;
+  int32_t* list = list_[wv];
+  const int32_t nc = g.nc;
+  const int32_t cz = (int32_t)(cidx % nc), cy = (int32_t)((cidx / nc) % nc), cx = (int32_t)(cidx / ((int64_t)nc * nc));
+  const int32_t T = fill_stencil_window(w, g, cx, cy, cz, 0, list, lane);
+  if (T > kListCap) {
+    for (int32_t t = t0 + lane; t < t1; t += 64) {
+      w.cnt[t] = -1;
+      w.fb[atomicAdd(w.nfb, 1)] = t;
+    }
+    return;
+  }
+  const int32_t C = (T + 63) / 64;
+  wave_sync();
+  for (int32_t g0 = t0; g0 < t1; g0 += kTgtGroup) {
+    const int32_t mg = min(kTgtGroup, t1 - g0);
+    if (lane < mg) {
+      const double4 me = w.pq[g0 + lane];
+      tpos_[wv][lane][0] = me.x;
+      tpos_[wv][lane][1] = me.y;
+      tpos_[wv][lane][2] = me.z;
+      nsg_[wv][lane] = 0;
+      ncg_[wv][lane] = 0;
+    }
+    wave_sync();
+    // pass 1, the next chunk's candidates in flight while this one is classified
+    int32_t un = lane < T ? list[lane] : -1;
+    double4 on = un >= 0 ? w.pq[un] : make_double4(0.0, 0.0, 0.0, 0.0);
+    for (int32_t c = 0; c < C; ++c) {
+      const int32_t u = un;
+      const double4 o = on;
+      if (c + 1 < C) {
+        const int32_t f = (c + 1) * 64 + lane;
+        un = f < T ? list[f] : -1;
+        if (un >= 0) on = w.pq[un];
+      }
+      for (int32_t k = 0; k < mg; ++k) {
+        double dx, dy, dz;
+        const double r2 = separation(tpos_[wv][k][0], tpos_[wv][k][1], tpos_[wv][k][2], o, a.L, a.invL, dx, dy, dz);
+        const uint64_t cm = __ballot(u >= 0 && r2 < a.rc2 && u != g0 + k);
+        const uint64_t sm = __ballot(u >= 0 && r2 >= a.rc2 && r2 <= a.rs2);
+        if (lane == 0) {
+          mask_[wv][k][c][0] = cm;
+          mask_[wv][k][c][1] = sm;
+          const int32_t before = nsg_[wv][k];
+          pre_[wv][k][c] = before;
+          nsg_[wv][k] = before + __popcll(sm);
+          ncg_[wv][k] += __popcll(cm);
+        }
+      }
+    }
+    wave_sync();
+    for (int32_t k = 0; k < mg; ++k) {
+      const int32_t t = g0 + k;
+      const int32_t ns = __builtin_amdgcn_readfirstlane(nsg_[wv][k]);
+      const int32_t ncore = __builtin_amdgcn_readfirstlane(ncg_[wv][k]);
+      const bool sub = ns > a.p;
+      const int32_t total = ncore + (sub ? a.p : ns);
+      if (total > a.Q) {
+        if (lane == 0) {
+          w.cnt[t] = -1;
+          w.fb[atomicAdd(w.nfb, 1)] = t;
+        }
+        continue;
+      }
+      uint32_t* out = w.slot + (int64_t)t * a.Q;
+      int32_t pos0 = 0;
+      for (int32_t c = 0; c < C; ++c) {
+        const uint64_t cm = mask_[wv][k][c][0], sm = mask_[wv][k][c][1];
+        const uint64_t take = sub ? cm : (cm | sm);
+        if (take == 0) continue;
+        if ((take >> lane) & 1)
+          out[pos0 + lanes_below(take)] = (uint32_t)list[c * 64 + lane] | (((sm >> lane) & 1) ? 0x80000000u : 0u);
+        pos0 += __popcll(take);
+      }
+      if (sub) {
+        const double uoff = w.ru[t];
+        for (int32_t b = lane; b < a.p; b += 64) {
+          const int32_t r = batch_pos(b, uoff, ns, a.p);
+          int32_t cc = 0;
+          for (int32_t c = 1; c < C; ++c) cc = pre_[wv][k][c] <= r ? c : cc;
+          const int32_t bit = select_bit(mask_[wv][k][cc][1], r - pre_[wv][k][cc]);
+          out[pos0 + b] = (uint32_t)list[cc * 64 + bit] | 0x80000000u;
+        }
+      }
+      if (lane == 0) {
+        w.cnt[t] = total;
+        w.tns[t] = ns;
+      }
+    }
+  }
+}
+
+// Pair forces: one lane per target (cell order), its slot's pairs added in slot order, shell
+// pairs times N_s / p.
+__global__ __launch_bounds__(kRblBlock) void rbl_pair_kernel(RblWs w, RblArgs a, double* __restrict__ F,
+                                                             int32_t* __restrict__ ns_out) {
+  const int32_t nb = (int32_t)((a.n + kRblBlock - 1) / kRblBlock), nb8 = (nb + 7) / 8;
+  const int32_t blk = (int32_t)(blockIdx.x & 7) * nb8 + (int32_t)(blockIdx.x >> 3);
+  const int64_t t = (int64_t)blk * kRblBlock + threadIdx.x;
+  if (blk >= nb || t >= a.n) return;
+  const int32_t cnt = w.cnt[t];
+  if (cnt < 0) return;
+  const double4 me = w.pq[t];
+  const double2 mlj = w.lj[t];
+  const int32_t i = w.idx[t];
+  const int32_t ns = w.tns[t];
+  const double wgt = ns > a.p ? (double)ns / (double)a.p : 1.0;
+  const uint32_t* e = w.slot + t * a.Q;
+  double ax = 0.0, ay = 0.0, az = 0.0;
+  // software pipeline: pair j + 1's data and pair j + 2's entry are in flight while pair j
+  // is evaluated
+  uint32_t en = cnt > 0 ? e[0] : 0u;
+  double4 on = make_double4(0.0, 0.0, 0.0, 0.0);
+  double2 ljn = make_double2(0.0, 0.0);
+  if (cnt > 0) {
+    on = w.pq[en & 0x7fffffffu];
+    ljn = w.lj[en & 0x7fffffffu];
+  }
+  uint32_t enn = cnt > 1 ? e[1] : 0u;
+  for (int32_t j = 0; j < cnt; ++j) {
+    const uint32_t ej = en;
+    const double4 o = on;
+    const double2 olj = ljn;
+    if (j + 1 < cnt) {
+      en = enn;
+      on = w.pq[en & 0x7fffffffu];
+      ljn = w.lj[en & 0x7fffffffu];
+      if (j + 2 < cnt) enn = e[j + 2];
+    }
+    double dx, dy, dz;
+    const double r2 = separation(me.x, me.y, me.z, o, a.L, a.invL, dx, dy, dz);
+    double px = 0.0, py = 0.0, pz = 0.0;
+    pair_force_add(me.w, o.w, mlj.x, olj.x, mlj.y, olj.y, a.alpha, a.sqa, a.tsap, dx, dy, dz, r2, px, py, pz);
+    const double wt = (ej >> 31) ? wgt : 1.0;
+    ax += wt * px;
+    ay += wt * py;
+    az += wt * pz;
+  }
+  F[i] = ax;
+  F[a.n + i] = ay;
+  F[2 * a.n + i] = az;
+  if (ns_out != nullptr) ns_out[i] = ns;
+}
+
+// Fallback for the targets the selection left (a stencil longer than kListCap, or more than
+// Q pairs): one wave per target, the stencil streamed in windows of kListCap positions and
+// classified twice (N_s, then ranks); each shell member's rank is tested against the draws
+// near floor(r p / N_s - u); the pairs go through an LDS queue evaluated 64 at a time, each
+// lane summing its pairs, and a fixed butterfly sums the lanes.
+__global__ __launch_bounds__(kRblBlock) void rbl_fallback_kernel(RblWs w, RblArgs a, RblGrid g, double* __restrict__ F,
+                                                                 int32_t* __restrict__ ns_out) {
+  __shared__ int32_t list_[kRblWaves][kListCap];
+  __shared__ uint32_t queue_[kRblWaves][64];
+  __shared__ int32_t batch_[kRblWaves][kBatchCap];
+  const int32_t nfb = __builtin_amdgcn_readfirstlane(*w.nfb);
+  const int32_t lane = (int32_t)(threadIdx.x & 63);
+  const int32_t wv = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+  int32_t* list = list_[wv];
+  uint32_t* queue = queue_[wv];
+  int32_t* batch = batch_[wv];
+  const int32_t nc = g.nc;
+  for (int32_t s = (int32_t)blockIdx.x * kRblWaves + wv; s < nfb; s += (int32_t)gridDim.x * kRblWaves) {
+    const int32_t t = __builtin_amdgcn_readfirstlane(w.fb[s]);
+    const int32_t i = w.idx[t];
+    const int32_t cidx = w.cell[i];
+    const int32_t cz = cidx % nc, cy = (cidx / nc) % nc, cx = cidx / (nc * nc);
+    const double4 me = w.pq[t];
+    const double2 mlj = w.lj[t];
+    wave_sync();
+    const int32_t T = fill_stencil_window(w, g, cx, cy, cz, 0, list, lane);
+    // fn(u, core, shell) for every stencil position, 64 at a time, window by window
+    auto classified = [&](auto&& fn) {
+      for (int32_t W0 = 0; W0 < T; W0 += kListCap) {
+        wave_sync();
+        fill_stencil_window(w, g, cx, cy, cz, W0, list, lane);
+        wave_sync();
+        const int32_t W1 = min(T, W0 + kListCap);
+        for (int32_t f0 = W0; f0 < W1; f0 += 64) {
+          const int32_t f = f0 + lane;
+          const int32_t u = f < W1 ? list[f - W0] : t;
+          double dx, dy, dz;
+          const double r2 = separation(me.x, me.y, me.z, w.pq[u], a.L, a.invL, dx, dy, dz);
+          fn(u, r2 < a.rc2 && u != t, r2 >= a.rc2 && r2 <= a.rs2);
+        }
+      }
+    };
+    int32_t ns = 0;
+    classified([&](int32_t, bool, bool shell) { ns += __popcll(__ballot(shell)); });
+    const bool sub = ns > a.p;
+    const double uoff = w.ru[t];
+    const double wgt = sub ? (double)ns / (double)a.p : 1.0;
+    const double slope = (double)a.p / (double)ns;
+    const bool listed = sub && a.p <= kBatchCap;
+    if (listed) {
+      wave_sync();
+      for (int32_t b = lane; b < a.p; b += 64) batch[b] = batch_pos(b, uoff, ns, a.p);
+      wave_sync();
+    }
+    // whether shell rank r is a draw's: the draw that can land on r is within one of
+    // floor(r p / N_s - u)
+    auto in_batch = [&](int32_t r) {
+      const int32_t bc = (int32_t)floor((double)r * slope - uoff);
+      bool hit = false;
+      for (int32_t b = bc - 1; b <= bc + 1; ++b)
+        if (b >= 0 && b < a.p) hit |= (listed ? batch[b] : batch_pos(b, uoff, ns, a.p)) == r;
+      return hit;
+    };
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    auto flush = [&](int32_t nq) {
+      if (lane < nq) {
+        const uint32_t e = queue[lane];
+        const int32_t u = (int32_t)(e & 0x7fffffffu);
+        const double4 o = w.pq[u];
+        const double2 olj = w.lj[u];
+        double dx, dy, dz;
+        const double r2 = separation(me.x, me.y, me.z, o, a.L, a.invL, dx, dy, dz);
+        double px = 0.0, py = 0.0, pz = 0.0;
+        pair_force_add(me.w, o.w, mlj.x, olj.x, mlj.y, olj.y, a.alpha, a.sqa, a.tsap, dx, dy, dz, r2, px, py, pz);
+        const double wt = (e >> 31) ? wgt : 1.0;
+        ax += wt * px;
+        ay += wt * py;
+        az += wt * pz;
+      }
+    };
+    int32_t qn = 0, rank0 = 0;
+    classified([&](int32_t u, bool core, bool shell) {
+      const uint64_t M = __ballot(shell);
+      const bool use = core || (shell && (!sub || in_batch(rank0 + lanes_below(M))));
+      rank0 += __popcll(M);
+      const uint64_t U = __ballot(use);
+      const int32_t cnt = __popcll(U);
+      if (cnt == 0) return;
+      const int32_t pos = qn + lanes_below(U);
+      const uint32_t e = (uint32_t)u | (shell ? 0x80000000u : 0u);
+      if (use && pos < 64) queue[pos] = e;
+      if (qn + cnt >= 64) {
+        wave_sync();
+        flush(64);
+        wave_sync();
+        if (use && pos >= 64) queue[pos - 64] = e;
+        qn += cnt - 64;
+      } else {
+        qn += cnt;
+      }
+    });
+    wave_sync();
+    flush(qn);
+    for (int o = 1; o < 64; o <<= 1) {
+      ax += __shfl_xor(ax, o, 64);
+      ay += __shfl_xor(ay, o, 64);
+      az += __shfl_xor(az, o, 64);
+    }
+    if (lane == 0) {
+      F[i] = ax;
+      F[a.n + i] = ay;
+      F[2 * a.n + i] = az;
+      if (ns_out != nullptr) ns_out[i] = ns;
+    }
+  }
+}
+
+// Fixed-order sums of 3-vectors: block b adds entries [b per, (b + 1) per) of src (thread t
+// takes every 256th from t, then a fixed tree) and writes scale times the sum to dst[3 b + d].
+// Entry k, component d is src[d * stride + k] (SOA) or src[3 k + d].  Two launches, the first
+// over the forces, give F^corr = -(1/N) sum_i F_i.
+template <bool SOA>
+__global__ __launch_bounds__(kRblBlock) void rbl_sum3_kernel(const double* __restrict__ src, int64_t stride, int64_t nsrc,
+                                                             int64_t per, double scale, double* __restrict__ dst) {
   __shared__ double red[3][kRblBlock];
   double s[3] = {0.0, 0.0, 0.0};
-  for (int32_t b = threadIdx.x; b < nblocks; b += kRblBlock)
-    for (int d = 0; d < 3; ++d) s[d] += w.partial[3 * (int64_t)b + d];
+  const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(b0 + per, nsrc);
+  for (int64_t b = b0 + threadIdx.x; b < b1; b += kRblBlock)
+    for (int d = 0; d < 3; ++d) s[d] += SOA ? src[d * stride + b] : src[3 * b + d];
   for (int d = 0; d < 3; ++d) red[d][threadIdx.x] = s[d];
   __syncthreads();
   for (int k = kRblBlock / 2; k > 0; k >>= 1) {
@@ -346,7 +649,7 @@ __global__ __launch_bounds__(kRblBlock) void rbl_corr_kernel(RblWs w, int32_t nb
       for (int d = 0; d < 3; ++d) red[d][threadIdx.x] += red[d][threadIdx.x + k];
     __syncthreads();
   }
-  if (threadIdx.x < 3) w.corr[threadIdx.x] = n > 0 ? -red[threadIdx.x][0] / (double)n : 0.0;
+  if (threadIdx.x < 3) dst[3 * (int64_t)blockIdx.x + threadIdx.x] = scale * red[threadIdx.x][0];
 }
 
 __global__ __launch_bounds__(kRblBlock) void rbl_apply_kernel(const double* __restrict__ corr, int64_t n,
@@ -370,23 +673,37 @@ struct rbl_plan {
   RblGrid grid;
   int64_t ncell = 0;
   int32_t nscan = 0;     // scan blocks
-  int32_t nforce = 0;    // force blocks
-  size_t off[14] = {};
+  int32_t nsel = 0;      // select blocks (kRblWaves cells each)
+  int32_t Q = 0;         // pair slots per particle
+  size_t off[17] = {};
   size_t bytes = 0;
 };
 
 namespace {
 
+// Slots per particle: room for the mean core count and the smaller of p and the mean shell
+// count of a uniform system, each with a Poisson allowance m + 6 sqrt(m) + 16; a particle
+// with more pairs takes the fallback.
+int32_t pair_slots(const rbl_params& q) {
+  const double dens = (double)q.N / (q.L * q.L * q.L);
+  const double vc = 4.0 / 3.0 * kRblPi * q.r_c * q.r_c * q.r_c;
+  const double vs = 4.0 / 3.0 * kRblPi * q.r_s * q.r_s * q.r_s - vc;
+  auto allow = [](double m) { return m + 6.0 * std::sqrt(m) + 16.0; };
+  const double k = std::ceil(allow(dens * vc) + std::min((double)q.p, allow(dens * vs)));
+  return (int32_t)std::min(k, 65536.0);
+}
+
 void rbl_layout(rbl_plan* p) {
-  const int64_t n = p->prm.N, nc = p->ncell;
-  const size_t sizes[14] = {
-      sizeof(int32_t) * (size_t)nc, sizeof(int32_t) * (size_t)nc, sizeof(int32_t) * (size_t)(nc + 1),
-      sizeof(int32_t) * (size_t)(p->nscan + 1), sizeof(int32_t) * (size_t)n, sizeof(int32_t) * (size_t)n,
-      sizeof(double) * (size_t)n, sizeof(double) * (size_t)n, sizeof(double) * (size_t)n,
-      sizeof(double) * (size_t)n, sizeof(double) * (size_t)n, sizeof(double) * (size_t)n,
-      sizeof(double) * 3 * (size_t)p->nforce, sizeof(double) * 3};
+  const size_t n = (size_t)p->prm.N, nc = (size_t)p->ncell;
+  const size_t sizes[17] = {
+      sizeof(int32_t) * nc,        sizeof(int32_t) * nc,           sizeof(int32_t) * (nc + 1),
+      sizeof(int32_t) * (size_t)(p->nscan + 1), sizeof(int32_t) * n, sizeof(int32_t) * n,
+      sizeof(double4) * n,         sizeof(double2) * n,            sizeof(int2) * nc,
+      sizeof(double) * n,          sizeof(uint32_t) * n * (size_t)p->Q, sizeof(int32_t) * n,
+      sizeof(int32_t) * n,         sizeof(int32_t) * n,            sizeof(int32_t),
+      sizeof(double) * 3 * kCorrBlocks, sizeof(double) * 3};
   size_t o = 0;
-  for (int k = 0; k < 14; ++k) {
+  for (int k = 0; k < 17; ++k) {
     p->off[k] = o;
     o = rbl_align(o + std::max<size_t>(sizes[k], 1));
   }
@@ -402,14 +719,17 @@ RblWs rbl_view(const rbl_plan* p, void* ws) {
   w.bsum = reinterpret_cast<int32_t*>(b + p->off[3]);
   w.cell = reinterpret_cast<int32_t*>(b + p->off[4]);
   w.idx = reinterpret_cast<int32_t*>(b + p->off[5]);
-  w.xs = reinterpret_cast<double*>(b + p->off[6]);
-  w.ys = reinterpret_cast<double*>(b + p->off[7]);
-  w.zs = reinterpret_cast<double*>(b + p->off[8]);
-  w.qs = reinterpret_cast<double*>(b + p->off[9]);
-  w.es = reinterpret_cast<double*>(b + p->off[10]);
-  w.ss = reinterpret_cast<double*>(b + p->off[11]);
-  w.partial = reinterpret_cast<double*>(b + p->off[12]);
-  w.corr = reinterpret_cast<double*>(b + p->off[13]);
+  w.pq = reinterpret_cast<double4*>(b + p->off[6]);
+  w.lj = reinterpret_cast<double2*>(b + p->off[7]);
+  w.range = reinterpret_cast<int2*>(b + p->off[8]);
+  w.ru = reinterpret_cast<double*>(b + p->off[9]);
+  w.slot = reinterpret_cast<uint32_t*>(b + p->off[10]);
+  w.cnt = reinterpret_cast<int32_t*>(b + p->off[11]);
+  w.tns = reinterpret_cast<int32_t*>(b + p->off[12]);
+  w.fb = reinterpret_cast<int32_t*>(b + p->off[13]);
+  w.nfb = reinterpret_cast<int32_t*>(b + p->off[14]);
+  w.partial = reinterpret_cast<double*>(b + p->off[15]);
+  w.corr = reinterpret_cast<double*>(b + p->off[16]);
   return w;
 }
 
@@ -443,7 +763,8 @@ rbe_status rbl_plan_create(const rbl_params* prm, rbl_plan** out) {
   p->grid = g;
   p->ncell = (int64_t)g.nc * g.nc * g.nc;
   p->nscan = (int32_t)((p->ncell + kScanChunk - 1) / kScanChunk);
-  p->nforce = (int32_t)blocks_for(q.N);
+  p->nsel = (int32_t)((p->ncell + kRblWaves - 1) / kRblWaves);
+  p->Q = pair_slots(q);
   rbl_layout(p);
   *out = p;
   return RBE_OK;
@@ -456,6 +777,13 @@ rbe_status rbl_plan_grid(const rbl_plan* p, int32_t* cells_per_axis, int32_t* re
   *cells_per_axis = p->grid.nc;
   *reach = p->grid.R;
   *stencil_span = p->grid.span;
+  return RBE_OK;
+}
+
+rbe_status rbl_plan_capacity(const rbl_plan* p, int32_t* pairs_per_particle, int32_t* stencil_positions) {
+  if (!p || !pairs_per_particle || !stencil_positions) return fail(RBE_EINVAL, "NULL argument");
+  *pairs_per_particle = p->Q;
+  *stencil_positions = kListCap;
   return RBE_OK;
 }
 
@@ -479,21 +807,41 @@ rbe_status rbl_short_force(const rbl_plan* p, const double* x, const double* y, 
   const rbl_params& prm = p->prm;
   hipLaunchKernelGGL(rbl_zero_kernel, dim3(blocks_for(nc)), dim3(kRblBlock), 0, s, w.count, nc);
   hipLaunchKernelGGL(rbl_zero_kernel, dim3(blocks_for(nc)), dim3(kRblBlock), 0, s, w.fill, nc);
+  hipLaunchKernelGGL(rbl_zero_kernel, dim3(1), dim3(kRblBlock), 0, s, w.nfb, (int64_t)1);
   hipLaunchKernelGGL(rbl_cell_kernel, dim3(blocks_for(n)), dim3(kRblBlock), 0, s, x, y, z, n, prm.L, g.nc, w.cell,
                      w.count);
   hipLaunchKernelGGL(rbl_scan_sums_kernel, dim3((unsigned)p->nscan), dim3(kRblBlock), 0, s, w.count, nc, w.bsum);
   hipLaunchKernelGGL(rbl_scan_offsets_kernel, dim3(1), dim3(kRblBlock), 0, s, w.bsum, p->nscan);
   hipLaunchKernelGGL(rbl_scan_apply_kernel, dim3((unsigned)p->nscan), dim3(kRblBlock), 0, s, w.count, nc, w.bsum,
-                     w.start, n);
+                     w.start, w.range, n);
   hipLaunchKernelGGL(rbl_scatter_kernel, dim3(blocks_for(n)), dim3(kRblBlock), 0, s, w.cell, n, w.start, w.fill,
                      w.idx);
   hipLaunchKernelGGL(rbl_segment_sort_kernel, dim3(blocks_for(nc)), dim3(kRblBlock), 0, s, w.start, nc, w.idx);
-  hipLaunchKernelGGL(rbl_gather_kernel, dim3(blocks_for(n)), dim3(kRblBlock), 0, s, x, y, z, q, eps, sig, n, w);
-  const double sqa = std::sqrt(prm.alpha);
-  const double tsap = 2.0 * std::sqrt(prm.alpha / kRblPi);
-  hipLaunchKernelGGL(rbl_force_kernel, dim3((unsigned)p->nforce), dim3(kRblBlock), 0, s, w, n, prm.L, prm.alpha, sqa,
-                     tsap, prm.r_c * prm.r_c, prm.r_s * prm.r_s, prm.p, g, seed, step, F, ns);
-  hipLaunchKernelGGL(rbl_corr_kernel, dim3(1), dim3(kRblBlock), 0, s, w, p->nforce, n);
+  hipLaunchKernelGGL(rbl_gather_kernel, dim3(blocks_for(n)), dim3(kRblBlock), 0, s, x, y, z, q, eps, sig, n, seed,
+                     step, w);
+  RblArgs a;
+  a.n = n;
+  a.ncell = nc;
+  a.nblk = p->nsel;
+  a.nblk8 = (p->nsel + 7) / 8;
+  a.p = prm.p;
+  a.Q = p->Q;
+  a.L = prm.L;
+  a.invL = 1.0 / prm.L;
+  a.alpha = prm.alpha;
+  a.sqa = std::sqrt(prm.alpha);
+  a.tsap = 2.0 * std::sqrt(prm.alpha / kRblPi);
+  a.rc2 = prm.r_c * prm.r_c;
+  a.rs2 = prm.r_s * prm.r_s;
+  hipLaunchKernelGGL(rbl_select_kernel, dim3((unsigned)(8 * a.nblk8)), dim3(kRblBlock), 0, s, w, a, g);
+  const int64_t nbp = (n + kRblBlock - 1) / kRblBlock;
+  hipLaunchKernelGGL(rbl_pair_kernel, dim3((unsigned)(8 * ((nbp + 7) / 8))), dim3(kRblBlock), 0, s, w, a, F, ns);
+  hipLaunchKernelGGL(rbl_fallback_kernel, dim3(kFallbackBlocks), dim3(kRblBlock), 0, s, w, a, g, F, ns);
+  const int64_t per = (n + kCorrBlocks - 1) / kCorrBlocks;
+  const int64_t nb1 = (n + per - 1) / per;
+  hipLaunchKernelGGL(rbl_sum3_kernel<true>, dim3((unsigned)nb1), dim3(kRblBlock), 0, s, F, n, n, per, 1.0, w.partial);
+  hipLaunchKernelGGL(rbl_sum3_kernel<false>, dim3(1), dim3(kRblBlock), 0, s, w.partial, (int64_t)0, nb1, nb1,
+                     -1.0 / (double)n, w.corr);
   hipLaunchKernelGGL(rbl_apply_kernel, dim3(blocks_for(n)), dim3(kRblBlock), 0, s, w.corr, n, F);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "rbl_short_force launch");

@@ -481,6 +481,12 @@ class RBLPlan:
         check(self.lib.rbl_plan_grid(self.handle, *[ctypes.byref(a) for a in v]), "rbl_plan_grid")
         return tuple(a.value for a in v)
 
+    def capacity(self):
+        """(pair slots per particle, stencil positions per cell) of the fast path."""
+        v = [ctypes.c_int32() for _ in range(2)]
+        check(self.lib.rbl_plan_capacity(self.handle, *[ctypes.byref(a) for a in v]), "rbl_plan_capacity")
+        return tuple(a.value for a in v)
+
     def short_force(self, x, y, z, q, eps, sig, seed: int, step: int, F=None, ns=None, stream=None):
         """(F (3, N) FP64, N_s (N,) int32) for one evaluation; enqueued without synchronisation."""
         for name, t in (("x", x), ("y", y), ("z", z), ("q", q), ("eps", eps), ("sig", sig)):

@@ -8,6 +8,7 @@
   * without a GPU, device calls report RBE_ENODEV.
 """
 import ctypes
+import math
 import os
 import re
 
@@ -256,6 +257,16 @@ def test_rbl_plan_validation_and_grid():
     nc, R, span = (a.value for a in v)
     assert (nc, R, span) == (8, 2, 5)                    # h = 5 = r_c, reach ceil(10 / 5)
     assert lib.rbl_plan_workspace_bytes(h) % 256 == 0
+    # pair slots: mean core and min(p, mean shell) counts of the uniform density, each with
+    # the allowance m + 6 sqrt(m) + 16
+    c = [ctypes.c_int32() for _ in range(2)]
+    assert lib.rbl_plan_capacity(h, *[ctypes.byref(a) for a in c]) == 0
+    dens = 1000 / 40.0 ** 3
+    mc, ms = dens * 4 / 3 * math.pi * 5.0 ** 3, dens * 4 / 3 * math.pi * (10.0 ** 3 - 5.0 ** 3)
+    allow = lambda m: m + 6 * math.sqrt(m) + 16
+    assert c[0].value == math.ceil(allow(mc) + min(10, allow(ms))) and c[1].value == 1024
+    assert lib.rbl_plan_workspace_bytes(h) >= 1000 * c[0].value * 4
+    assert lib.rbl_plan_capacity(None, *[ctypes.byref(a) for a in c]) == _lib.RBE_EINVAL
     lib.rbl_plan_destroy(h)
     st, h = _rbl(L=21.0, rc=5.0, rs=10.0)                # 4 cells per axis: the stencil wraps
     assert st == 0

@@ -2,8 +2,10 @@
 
   * whole systems (every force, every N_s) on the same batch offsets: the primitive
     electrolyte at the paper's density with p = 30 and 100, unequal LJ parameters, a
-    particle count off the block size, a box whose stencil wraps, and a batch larger than
-    every shell (the exact truncated force);
+    particle count off the block size, a box whose stencil wraps, a batch larger than
+    every shell (the exact truncated force), a dense box whose cells hold more than one
+    group of targets and whose stencil is streamed in windows, and a packed cluster whose
+    particles have more pairs than the fast path's slots;
   * the 1M-particle benchmark system: N_s exact and the raw force differences F_i - F_0 of
     sampled particles (the momentum correction is one vector for all) against the oracle's
     brute-force raw forces of those particles, and sum_i F_i = 0;
@@ -39,6 +41,7 @@ CASES = [
     (250, 0.01, 0.06, 6.0, 12.0, 30, False),     # L = 29.2: 4 cells per axis, the stencil wraps
     (1500, 0.01, 0.06, 6.0, 12.0, 4000, False),  # batch larger than every shell: exact force
     (2500, 0.3, 0.3, 2.5, 5.0, 10, True),        # denser: about 5 particles per cell
+    (2000, 1.0, 0.3, 2.5, 5.0, 20, True),        # 16 per cell, stencil of 2000 > 1024 positions
 ]
 
 
@@ -60,6 +63,30 @@ def test_rbl_parity(n, density, alpha, rc, rs, p, unequal):
     note(f"  force rel RMS {ef:.2e}, max {em:.2e}, mean N_s {ns.mean():.1f}")
     assert ef < 1e-12 and em < 1e-11
     assert np.all(np.abs(F.sum(axis=1)) < 1e-11 * np.abs(F).sum(axis=1))
+    plan.close()
+
+
+def test_rbl_parity_crowded():
+    """80 particles packed into a ball (density about 0.2 inside a box at 0.01): each has more
+    core pairs than the plan's pair slots hold, so they take the slower path."""
+    n, alpha, rc, rs, p = 2000, 0.06, 6.0, 12.0, 30
+    s = ri.primitive_electrolyte(n, 0.01, 4242)
+    g = np.random.default_rng(7)
+    pts = np.array([(i, j, k) for i in range(-3, 4) for j in range(-3, 4) for k in range(-3, 4)], float) * 1.6
+    pts = pts[np.argsort(np.linalg.norm(pts, axis=1), kind="stable")][:80]
+    pts += g.uniform(-0.2, 0.2, pts.shape) + s.L / 2
+    s.x[:80], s.y[:80], s.z[:80] = pts[:, 0], pts[:, 1], pts[:, 2]
+    seed, step = 31, 2
+    plan, X, F, ns = _run(s, alpha, rc, rs, p, seed, step)
+    slots, _ = plan.capacity()
+    note(f"case rbl crowded: pair slots {slots}")
+    assert slots < 79
+    F_ref, ns_ref = oracle.rbl_short_force(s.x, s.y, s.z, s.q, s.eps, s.sig, s.L, alpha, rc, rs, p,
+                                           oracle.rbl_offsets(seed, step, n))
+    assert np.array_equal(ns, ns_ref)
+    ef, em = force_err(F, F_ref), max_err(F, F_ref)
+    note(f"  force rel RMS {ef:.2e}, max {em:.2e}")
+    assert ef < 1e-12 and em < 1e-11
     plan.close()
 
 
