@@ -41,7 +41,19 @@ struct RblGrid {
   int32_t R;      // stencil reach in cells
   int32_t span;   // stencil cells per axis: 2R + 1, or nc when that would wrap
   int32_t wrap;   // 1 when the stencil covers every cell of an axis
+  float inv_span;       // 1 / span
+  double inv_nc, inv_nc2;   // 1 / nc, 1 / nc^2
 };
+
+// One particle in cell order: position and charge, sqrt(eps) and sigma, and the position in
+// 32-bit fixed point (frac(x / L) 2^32, so that a wrapping difference is the minimum image)
+// with the particle index.  64 bytes: a pair's data is one cache-line half.
+struct alignas(64) RblRec {
+  double4 pq;
+  double2 lj;
+  uint4 fx;
+};
+static_assert(sizeof(RblRec) == 64, "RblRec is 64 bytes");
 
 struct RblWs {
   int32_t* count;
@@ -50,8 +62,7 @@ struct RblWs {
   int32_t* bsum;     // scan block sums
   int32_t* cell;     // N, by particle index
   int32_t* idx;      // N: particle index at each cell-order position
-  double4* pq;       // N, in cell order: x, y, z, q
-  double2* lj;       // N, in cell order: sqrt(eps), sig
+  RblRec* rec;       // N, in cell order
   int2* range;       // ncell: first and one-past-last cell-order position of each cell
   double* ru;        // N, in cell order: the particle's batch offset u_i
   uint32_t* slot;    // N x Q pair entries, in cell order
@@ -184,16 +195,26 @@ __global__ __launch_bounds__(kRblBlock) void rbl_segment_sort_kernel(const int32
   }
 }
 
+// floor(frac(x / L) 2^32), below 2^32.
+__device__ inline uint32_t fixed_coord(double x, double L) {
+  const double s = x / L;
+  const double v = (s - floor(s)) * 4294967296.0;
+  return v < 4294967295.0 ? (uint32_t)v : 0xffffffffu;
+}
+
 __global__ __launch_bounds__(kRblBlock) void rbl_gather_kernel(const double* __restrict__ x, const double* __restrict__ y,
                                                                const double* __restrict__ z, const double* __restrict__ q,
                                                                const double* __restrict__ eps,
-                                                               const double* __restrict__ sig, int64_t n, uint64_t seed,
-                                                               uint64_t step, RblWs w) {
+                                                               const double* __restrict__ sig, int64_t n, double L,
+                                                               uint64_t seed, uint64_t step, RblWs w) {
   const int64_t t = (int64_t)blockIdx.x * kRblBlock + threadIdx.x;
   if (t >= n) return;
   const int32_t i = w.idx[t];
-  w.pq[t] = make_double4(x[i], y[i], z[i], q[i]);
-  w.lj[t] = make_double2(sqrt(eps[i]), sig[i]);
+  RblRec r;
+  r.pq = make_double4(x[i], y[i], z[i], q[i]);
+  r.lj = make_double2(sqrt(eps[i]), sig[i]);
+  r.fx = make_uint4(fixed_coord(x[i], L), fixed_coord(y[i], L), fixed_coord(z[i], L), (uint32_t)i);
+  w.rec[t] = r;
   U64x4 ctr = {{(uint64_t)i, 0ull, 3ull, 0ull}};
   w.ru[t] = u01_53(philox4x64_10(ctr, seed, step).v[0]);
 }
@@ -240,16 +261,24 @@ __device__ inline void pair_force_add(double qi, double qj, double rei, double r
   fz += g * dz;
 }
 
-__device__ inline int32_t wrap_cell(int32_t c, int32_t nc) {
-  const int32_t m = c % nc;
-  return m < 0 ? m + nc : m;
+// c mod nc for c in [-nc, 2 nc): stencil offsets stay within one period.
+__device__ inline int32_t wrap_cell(int32_t c, int32_t nc) { return c < 0 ? c + nc : (c >= nc ? c - nc : c); }
+
+// Cell coordinates of cell index c = (cx nc + cy) nc + cz, through products with 1 / nc^2
+// and 1 / nc in FP64: the quotients' fractional parts are at least 0.5 / nc^2 away from an
+// integer, far beyond the rounding.
+__device__ inline void cell_coords(int32_t c, const RblGrid& g, int32_t& cx, int32_t& cy, int32_t& cz) {
+  cx = (int32_t)(((double)c + 0.5) * g.inv_nc2);
+  const int32_t r = c - cx * g.nc * g.nc;
+  cy = (int32_t)(((double)r + 0.5) * g.inv_nc);
+  cz = r - cy * g.nc;
 }
 
 constexpr int kRblWaves = kRblBlock / 64;   // waves per block
-constexpr int kListCap = 1024;              // stencil positions held in LDS per wave
+constexpr int kListCap = 512;               // stencil positions held in LDS per wave
 constexpr int kBatchCap = 256;              // batch positions held in LDS per wave (fallback)
-constexpr int kTgtGroup = 8;                // targets classified together
-constexpr int kMaxChunks = kListCap / 64;
+static_assert(kListCap / 64 <= 32, "one bit per chunk in a 32-bit word");
+constexpr int kTgtGroup = 4;                // targets classified together
 constexpr int kFallbackBlocks = 512;
 constexpr int kCorrBlocks = 256;
 
@@ -258,31 +287,13 @@ struct RblArgs {
   int32_t nblk, nblk8;   // blocks of the select kernel and that count over the 8 XCDs, rounded up
   int32_t p, Q;          // batch size, pair slots per particle
   double L, invL, alpha, sqa, tsap, rc2, rs2;
+  // r_c^2 and r_s^2 in fixed-point units^2, each widened to a band [lo, hi] that holds every
+  // squared distance the fixed-point FP32 estimate cannot place on one side
+  float rc2lo, rc2hi, rs2lo, rs2hi;
 };
 
 __device__ inline int32_t lanes_below(uint64_t m) {
   return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-// Position of the j-th (from 0) set bit of m; m holds more than j set bits.
-__device__ inline int32_t select_bit(uint64_t m, int32_t j) {
-  uint32_t v = (uint32_t)m;
-  int32_t pos = 0;
-  const int32_t c32 = __popc(v);
-  if (j >= c32) {
-    j -= c32;
-    v = (uint32_t)(m >> 32);
-    pos = 32;
-  }
-  for (int wdt = 16; wdt >= 1; wdt >>= 1) {
-    const int32_t c = __popc(v & ((1u << wdt) - 1u));
-    if (j >= c) {
-      j -= c;
-      v >>= wdt;
-      pos += wdt;
-    }
-  }
-  return pos;
 }
 
 // LDS written by some lanes of a wave and read by others: keep the accesses in order.
@@ -307,9 +318,11 @@ __device__ int32_t fill_stencil_window(const RblWs& w, const RblGrid& g, int32_t
     const int32_t sidx = s0 + lane;
     int32_t sb = 0, sl = 0;
     if (sidx < nseg) {
-      const int32_t row = sidx / nsr, piece = sidx - row * nsr;
-      const int32_t a = row / span, b = row - a * span;
-      const int64_t base = ((int64_t)wrap_cell(cx + o0 + a, nc) * nc + wrap_cell(cy + o0 + b, nc)) * nc;
+      const int32_t row = nsr == 2 ? sidx >> 1 : sidx, piece = sidx - row * nsr;
+      // row / span through 1 / span in FP32: (row + 1/2) / span is at least 1 / (2 span)
+      // from an integer, and span^2 < 2^19
+      const int32_t a = (int32_t)(((float)row + 0.5f) * g.inv_span), b = row - a * span;
+      const int32_t base = (wrap_cell(cx + o0 + a, nc) * nc + wrap_cell(cy + o0 + b, nc)) * nc;
       const int32_t c0 = piece == 0 ? z0 : 0;
       const int32_t c1 = piece == 0 ? min(z0 + span, nc) : z0 + span - nc;
       sb = w.range[base + c0].x;
@@ -342,37 +355,37 @@ __device__ inline double separation(double xi, double yi, double zi, const doubl
   return dist2(dx, dy, dz);
 }
 
-// Selection: one wave per cell.  The lanes stream the cell's stencil (its cell-order
-// positions, in traversal order, held in LDS) 64 candidates at a time.  Pass 1, per group of
-// up to kTgtGroup particles of the cell with each candidate loaded once for the group,
-// classifies every candidate against every target into core and shell ballot masks kept in
-// LDS, with N_s, the core count and the shell members before each chunk.  Then each target
-// writes its pair entries -- cell-order index, top bit set for shell members -- into its
-// slot of Q entries: the core (and the whole shell when N_s <= p) by compaction of the
-// masks, and the batch one draw per lane, its shell rank floor((b + u) N_s / p) found through
-// the per-chunk counts and the set bits of that chunk's shell mask.  A cell whose stencil
-// exceeds kListCap positions, or a target with more than Q pairs, is left to the fallback.
+// Selection: one wave per cell.  The cell's stencil -- its cell-order positions in traversal
+// order, held in LDS -- is at most kListCap positions, streamed 64 at a time with the next
+// chunk's fixed-point coordinates in flight.  Pass 1, per group of up to kTgtGroup particles
+// of the cell, classifies every candidate against every target from the fixed-point
+// differences in FP32; each lane keeps one core bit and one shell bit per chunk and target;
+// where the estimate falls in a band around r_c^2 or r_s^2 the lane is classified afterwards
+// with the FP64 distance of the definition.  The batch draws mark their shell ranks
+// floor((b + u) N_s / p) in an LDS byte array, and one sweep over the chunks writes the pair
+// entries -- cell-order index, top bit set for shell members -- into the target's slot of Q
+// entries: every core member, and every shell member whose rank is marked (all of them when
+// N_s <= p).  A cell whose stencil exceeds kListCap positions, or a target with more than Q
+// pairs, is left to the fallback.
 __global__ __launch_bounds__(kRblBlock) void rbl_select_kernel(RblWs w, RblArgs a, RblGrid g) {
   __shared__ int32_t list_[kRblWaves][kListCap];
-  __shared__ uint64_t mask_[kRblWaves][kTgtGroup][kMaxChunks][2];
-  __shared__ int32_t pre_[kRblWaves][kTgtGroup][kMaxChunks];
-  __shared__ double tpos_[kRblWaves][kTgtGroup][3];
-  __shared__ int32_t nsg_[kRblWaves][kTgtGroup];
-  __shared__ int32_t ncg_[kRblWaves][kTgtGroup];
+  __shared__ uint64_t mark_[kRblWaves][kListCap / 8];   // one byte per shell rank
   // blocks are dealt to the XCDs in turn: give each XCD a contiguous run of cells
   const int32_t blk = (int32_t)(blockIdx.x & 7) * a.nblk8 + (int32_t)(blockIdx.x >> 3);
   if (blk >= a.nblk) return;
   const int32_t lane = (int32_t)(threadIdx.x & 63);
   const int32_t wv = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
-  const int64_t cidx = (int64_t)blk * kRblWaves + wv;
+  const int32_t cidx = blk * kRblWaves + wv;
   if (cidx >= a.ncell) return;
-  const int2 own = w.range[cidx];
+  const int2 own = w.range[cidx];   // in flight with the stencil's ranges
+  int32_t* list = list_[wv];
+  uint8_t* mark = reinterpret_cast<uint8_t*>(mark_[wv]);
+  mark_[wv][lane] = 0;
+  int32_t cx, cy, cz;
+  cell_coords(cidx, g, cx, cy, cz);
+  const int32_t T = fill_stencil_window(w, g, cx, cy, cz, 0, list, lane);
   const int32_t t0 = __builtin_amdgcn_readfirstlane(own.x), t1 = __builtin_amdgcn_readfirstlane(own.y);
   if (t1 <= t0) return;
-  int32_t* list = list_[wv];
-  const int32_t nc = g.nc;
-  const int32_t cz = (int32_t)(cidx % nc), cy = (int32_t)((cidx / nc) % nc), cx = (int32_t)(cidx / ((int64_t)nc * nc));
-  const int32_t T = fill_stencil_window(w, g, cx, cy, cz, 0, list, lane);
   if (T > kListCap) {
     for (int32_t t = t0 + lane; t < t1; t += 64) {
       w.cnt[t] = -1;
@@ -384,46 +397,98 @@ __global__ __launch_bounds__(kRblBlock) void rbl_select_kernel(RblWs w, RblArgs 
   wave_sync();
   for (int32_t g0 = t0; g0 < t1; g0 += kTgtGroup) {
     const int32_t mg = min(kTgtGroup, t1 - g0);
-    if (lane < mg) {
-      const double4 me = w.pq[g0 + lane];
-      tpos_[wv][lane][0] = me.x;
-      tpos_[wv][lane][1] = me.y;
-      tpos_[wv][lane][2] = me.z;
-      nsg_[wv][lane] = 0;
-      ncg_[wv][lane] = 0;
+    uint4 tf[kTgtGroup];
+    // bit c of cb[k] / sb[k]: this lane's candidate of chunk c is a core / shell member of
+    // target g0 + k; bit c of ac[k]: chunk c holds lanes left ambiguous for it
+    uint32_t cb[kTgtGroup], sb[kTgtGroup], ac[kTgtGroup];
+    int32_t nsk[kTgtGroup], nck[kTgtGroup];
+    // every load of the group is issued here: a wait for a load also waits for the stores
+    // before it, and the slot writes below are many
+    double ug[kTgtGroup];
+#pragma unroll
+    for (int k = 0; k < kTgtGroup; ++k) {
+      tf[k] = w.rec[g0 + min(k, mg - 1)].fx;
+      ug[k] = w.ru[g0 + min(k, mg - 1)];
+      cb[k] = sb[k] = ac[k] = 0;
+      nsk[k] = nck[k] = 0;
     }
-    wave_sync();
-    // pass 1, the next chunk's candidates in flight while this one is classified
     int32_t un = lane < T ? list[lane] : -1;
-    double4 on = un >= 0 ? w.pq[un] : make_double4(0.0, 0.0, 0.0, 0.0);
+    uint4 fn = un >= 0 ? w.rec[un].fx : make_uint4(0u, 0u, 0u, 0u);
     for (int32_t c = 0; c < C; ++c) {
       const int32_t u = un;
-      const double4 o = on;
+      const uint4 fo = fn;
       if (c + 1 < C) {
         const int32_t f = (c + 1) * 64 + lane;
         un = f < T ? list[f] : -1;
-        if (un >= 0) on = w.pq[un];
+        if (un >= 0) fn = w.rec[un].fx;
       }
-      for (int32_t k = 0; k < mg; ++k) {
-        double dx, dy, dz;
-        const double r2 = separation(tpos_[wv][k][0], tpos_[wv][k][1], tpos_[wv][k][2], o, a.L, a.invL, dx, dy, dz);
-        const uint64_t cm = __ballot(u >= 0 && r2 < a.rc2 && u != g0 + k);
-        const uint64_t sm = __ballot(u >= 0 && r2 >= a.rc2 && r2 <= a.rs2);
-        if (lane == 0) {
-          mask_[wv][k][c][0] = cm;
-          mask_[wv][k][c][1] = sm;
-          const int32_t before = nsg_[wv][k];
-          pre_[wv][k][c] = before;
-          nsg_[wv][k] = before + __popcll(sm);
-          ncg_[wv][k] += __popcll(cm);
+      const uint32_t bit = 1u << c;
+#pragma unroll
+      for (int k = 0; k < kTgtGroup; ++k) {
+        if (k < mg) {
+          const float fdx = (float)(int32_t)(tf[k].x - fo.x);
+          const float fdy = (float)(int32_t)(tf[k].y - fo.y);
+          const float fdz = (float)(int32_t)(tf[k].z - fo.z);
+          const float f2 = fdx * fdx + fdy * fdy + fdz * fdz;
+          const bool v = u >= 0;
+          const bool near = f2 < a.rc2lo;
+          const bool shell = v && f2 > a.rc2hi && f2 < a.rs2lo;
+          const bool core = v && near && u != g0 + k;
+          const bool amb = v && !near && !shell && !(f2 > a.rs2hi);
+          cb[k] |= core ? bit : 0u;
+          sb[k] |= shell ? bit : 0u;
+          nsk[k] += __popcll(__ballot(shell));
+          nck[k] += __popcll(__ballot(core));
+          ac[k] |= __ballot(amb) != 0 ? bit : 0u;
         }
       }
     }
-    wave_sync();
     for (int32_t k = 0; k < mg; ++k) {
       const int32_t t = g0 + k;
-      const int32_t ns = __builtin_amdgcn_readfirstlane(nsg_[wv][k]);
-      const int32_t ncore = __builtin_amdgcn_readfirstlane(ncg_[wv][k]);
+      uint32_t cbits = 0, sbits = 0, ambc = 0;
+      int32_t ns = 0, ncore = 0;
+      double uoff = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < kTgtGroup; ++kk) {
+        if (kk == k) {
+          cbits = cb[kk];
+          sbits = sb[kk];
+          ambc = ac[kk];
+          ns = nsk[kk];
+          ncore = nck[kk];
+          uoff = ug[kk];
+        }
+      }
+      if (ambc != 0) {
+        // the ambiguous lanes, with the FP64 distance of the definition
+        const double4 me = w.rec[t].pq;
+        const uint4 mf = w.rec[t].fx;
+        for (int32_t c = 0; c < C; ++c) {
+          if (((ambc >> c) & 1) == 0) continue;
+          const int32_t f = c * 64 + lane;
+          const int32_t u = f < T ? list[f] : -1;
+          bool core = false, shell = false;
+          if (u >= 0) {
+            const uint4 fo = w.rec[u].fx;
+            const float fdx = (float)(int32_t)(mf.x - fo.x);
+            const float fdy = (float)(int32_t)(mf.y - fo.y);
+            const float fdz = (float)(int32_t)(mf.z - fo.z);
+            const float f2 = fdx * fdx + fdy * fdy + fdz * fdz;
+            const bool near = f2 < a.rc2lo;
+            const bool sh = f2 > a.rc2hi && f2 < a.rs2lo;
+            if (!near && !sh && !(f2 > a.rs2hi)) {
+              double dx, dy, dz;
+              const double r2 = separation(me.x, me.y, me.z, w.rec[u].pq, a.L, a.invL, dx, dy, dz);
+              core = r2 < a.rc2 && u != t;
+              shell = r2 >= a.rc2 && r2 <= a.rs2;
+            }
+          }
+          cbits |= core ? (1u << c) : 0u;
+          sbits |= shell ? (1u << c) : 0u;
+          ns += __popcll(__ballot(shell));
+          ncore += __popcll(__ballot(core));
+        }
+      }
       const bool sub = ns > a.p;
       const int32_t total = ncore + (sub ? a.p : ns);
       if (total > a.Q) {
@@ -433,28 +498,28 @@ __global__ __launch_bounds__(kRblBlock) void rbl_select_kernel(RblWs w, RblArgs 
         }
         continue;
       }
+      if (sub) {
+        for (int32_t b = lane; b < a.p; b += 64) mark[batch_pos(b, uoff, ns, a.p)] = 1;
+        wave_sync();
+      }
       uint32_t* out = w.slot + (int64_t)t * a.Q;
-      int32_t pos0 = 0;
+      int32_t pos0 = 0, rank0 = 0;
       for (int32_t c = 0; c < C; ++c) {
-        const uint64_t cm = mask_[wv][k][c][0], sm = mask_[wv][k][c][1];
-        const uint64_t take = sub ? cm : (cm | sm);
-        if (take == 0) continue;
-        if ((take >> lane) & 1)
-          out[pos0 + lanes_below(take)] = (uint32_t)list[c * 64 + lane] | (((sm >> lane) & 1) ? 0x80000000u : 0u);
-        pos0 += __popcll(take);
+        const bool shell = (sbits >> c) & 1;
+        const uint64_t sm = __ballot(shell);
+        bool use = (cbits >> c) & 1;
+        if (shell) use = !sub || mark[rank0 + lanes_below(sm)] != 0;
+        const uint64_t U = __ballot(use);
+        if (use) out[pos0 + lanes_below(U)] = (uint32_t)list[c * 64 + lane] | (shell ? 0x80000000u : 0u);
+        pos0 += __popcll(U);
+        rank0 += __popcll(sm);
       }
       if (sub) {
-        const double uoff = w.ru[t];
-        for (int32_t b = lane; b < a.p; b += 64) {
-          const int32_t r = batch_pos(b, uoff, ns, a.p);
-          int32_t cc = 0;
-          for (int32_t c = 1; c < C; ++c) cc = pre_[wv][k][c] <= r ? c : cc;
-          const int32_t bit = select_bit(mask_[wv][k][cc][1], r - pre_[wv][k][cc]);
-          out[pos0 + b] = (uint32_t)list[cc * 64 + bit] | 0x80000000u;
-        }
+        wave_sync();
+        mark_[wv][lane] = 0;
       }
       if (lane == 0) {
-        w.cnt[t] = total;
+        w.cnt[t] = pos0;
         w.tns[t] = ns;
       }
     }
@@ -471,9 +536,9 @@ __global__ __launch_bounds__(kRblBlock) void rbl_pair_kernel(RblWs w, RblArgs a,
   if (blk >= nb || t >= a.n) return;
   const int32_t cnt = w.cnt[t];
   if (cnt < 0) return;
-  const double4 me = w.pq[t];
-  const double2 mlj = w.lj[t];
-  const int32_t i = w.idx[t];
+  const double4 me = w.rec[t].pq;
+  const double2 mlj = w.rec[t].lj;
+  const int32_t i = (int32_t)w.rec[t].fx.w;
   const int32_t ns = w.tns[t];
   const double wgt = ns > a.p ? (double)ns / (double)a.p : 1.0;
   const uint32_t* e = w.slot + t * a.Q;
@@ -484,8 +549,8 @@ __global__ __launch_bounds__(kRblBlock) void rbl_pair_kernel(RblWs w, RblArgs a,
   double4 on = make_double4(0.0, 0.0, 0.0, 0.0);
   double2 ljn = make_double2(0.0, 0.0);
   if (cnt > 0) {
-    on = w.pq[en & 0x7fffffffu];
-    ljn = w.lj[en & 0x7fffffffu];
+    on = w.rec[en & 0x7fffffffu].pq;
+    ljn = w.rec[en & 0x7fffffffu].lj;
   }
   uint32_t enn = cnt > 1 ? e[1] : 0u;
   for (int32_t j = 0; j < cnt; ++j) {
@@ -494,8 +559,8 @@ __global__ __launch_bounds__(kRblBlock) void rbl_pair_kernel(RblWs w, RblArgs a,
     const double2 olj = ljn;
     if (j + 1 < cnt) {
       en = enn;
-      on = w.pq[en & 0x7fffffffu];
-      ljn = w.lj[en & 0x7fffffffu];
+      on = w.rec[en & 0x7fffffffu].pq;
+      ljn = w.rec[en & 0x7fffffffu].lj;
       if (j + 2 < cnt) enn = e[j + 2];
     }
     double dx, dy, dz;
@@ -529,14 +594,13 @@ __global__ __launch_bounds__(kRblBlock) void rbl_fallback_kernel(RblWs w, RblArg
   int32_t* list = list_[wv];
   uint32_t* queue = queue_[wv];
   int32_t* batch = batch_[wv];
-  const int32_t nc = g.nc;
   for (int32_t s = (int32_t)blockIdx.x * kRblWaves + wv; s < nfb; s += (int32_t)gridDim.x * kRblWaves) {
     const int32_t t = __builtin_amdgcn_readfirstlane(w.fb[s]);
     const int32_t i = w.idx[t];
-    const int32_t cidx = w.cell[i];
-    const int32_t cz = cidx % nc, cy = (cidx / nc) % nc, cx = cidx / (nc * nc);
-    const double4 me = w.pq[t];
-    const double2 mlj = w.lj[t];
+    int32_t cx, cy, cz;
+    cell_coords(w.cell[i], g, cx, cy, cz);
+    const double4 me = w.rec[t].pq;
+    const double2 mlj = w.rec[t].lj;
     wave_sync();
     const int32_t T = fill_stencil_window(w, g, cx, cy, cz, 0, list, lane);
     // fn(u, core, shell) for every stencil position, 64 at a time, window by window
@@ -550,7 +614,7 @@ __global__ __launch_bounds__(kRblBlock) void rbl_fallback_kernel(RblWs w, RblArg
           const int32_t f = f0 + lane;
           const int32_t u = f < W1 ? list[f - W0] : t;
           double dx, dy, dz;
-          const double r2 = separation(me.x, me.y, me.z, w.pq[u], a.L, a.invL, dx, dy, dz);
+          const double r2 = separation(me.x, me.y, me.z, w.rec[u].pq, a.L, a.invL, dx, dy, dz);
           fn(u, r2 < a.rc2 && u != t, r2 >= a.rc2 && r2 <= a.rs2);
         }
       }
@@ -581,8 +645,8 @@ __global__ __launch_bounds__(kRblBlock) void rbl_fallback_kernel(RblWs w, RblArg
       if (lane < nq) {
         const uint32_t e = queue[lane];
         const int32_t u = (int32_t)(e & 0x7fffffffu);
-        const double4 o = w.pq[u];
-        const double2 olj = w.lj[u];
+        const double4 o = w.rec[u].pq;
+        const double2 olj = w.rec[u].lj;
         double dx, dy, dz;
         const double r2 = separation(me.x, me.y, me.z, o, a.L, a.invL, dx, dy, dz);
         double px = 0.0, py = 0.0, pz = 0.0;
@@ -693,12 +757,25 @@ int32_t pair_slots(const rbl_params& q) {
   return (int32_t)std::min(k, 65536.0);
 }
 
+// The band around R^2 (fixed-point units u = L / 2^32) outside which the FP32 estimate f2 of
+// a squared distance r^2 is on the same side of R^2 as r^2.  The floors of the two fixed
+// coordinates put each difference within 2 u of the exact one, so |DX^2 - d^2| <= 4|d| + 4
+// per axis and the sum is within 4 sqrt(3) r + 12 (u^2); the conversions to FP32, squares and
+// sums add a relative 3e-7.  At r near R that is a relative 6.93 / R + 12 / R^2 + 3e-7, R in
+// units; the band takes four times that plus 1e-6.
+void fixed_point_band(double R, double L, float& lo, float& hi) {
+  const double Ru = R * (4294967296.0 / L);
+  const double rel = 4.0 * (6.93 / Ru + 12.0 / (Ru * Ru) + 3e-7) + 1e-6;
+  lo = (float)(Ru * Ru * (1.0 - rel));
+  hi = (float)(Ru * Ru * (1.0 + rel));
+}
+
 void rbl_layout(rbl_plan* p) {
   const size_t n = (size_t)p->prm.N, nc = (size_t)p->ncell;
   const size_t sizes[17] = {
       sizeof(int32_t) * nc,        sizeof(int32_t) * nc,           sizeof(int32_t) * (nc + 1),
       sizeof(int32_t) * (size_t)(p->nscan + 1), sizeof(int32_t) * n, sizeof(int32_t) * n,
-      sizeof(double4) * n,         sizeof(double2) * n,            sizeof(int2) * nc,
+      sizeof(RblRec) * n,          1,                              sizeof(int2) * nc,
       sizeof(double) * n,          sizeof(uint32_t) * n * (size_t)p->Q, sizeof(int32_t) * n,
       sizeof(int32_t) * n,         sizeof(int32_t) * n,            sizeof(int32_t),
       sizeof(double) * 3 * kCorrBlocks, sizeof(double) * 3};
@@ -719,8 +796,7 @@ RblWs rbl_view(const rbl_plan* p, void* ws) {
   w.bsum = reinterpret_cast<int32_t*>(b + p->off[3]);
   w.cell = reinterpret_cast<int32_t*>(b + p->off[4]);
   w.idx = reinterpret_cast<int32_t*>(b + p->off[5]);
-  w.pq = reinterpret_cast<double4*>(b + p->off[6]);
-  w.lj = reinterpret_cast<double2*>(b + p->off[7]);
+  w.rec = reinterpret_cast<RblRec*>(b + p->off[6]);
   w.range = reinterpret_cast<int2*>(b + p->off[8]);
   w.ru = reinterpret_cast<double*>(b + p->off[9]);
   w.slot = reinterpret_cast<uint32_t*>(b + p->off[10]);
@@ -757,6 +833,9 @@ rbe_status rbl_plan_create(const rbl_params* prm, rbl_plan** out) {
   g.R = (int32_t)std::ceil(q.r_s / h);
   g.wrap = (2 * g.R + 1 > g.nc) ? 1 : 0;
   g.span = g.wrap ? g.nc : 2 * g.R + 1;
+  g.inv_span = 1.0f / (float)g.span;
+  g.inv_nc = 1.0 / (double)g.nc;
+  g.inv_nc2 = 1.0 / ((double)g.nc * (double)g.nc);
   rbl_plan* p = new (std::nothrow) rbl_plan();
   if (p == nullptr) return fail(RBE_EINVAL, "out of host memory");
   p->prm = q;
@@ -817,8 +896,8 @@ rbe_status rbl_short_force(const rbl_plan* p, const double* x, const double* y, 
   hipLaunchKernelGGL(rbl_scatter_kernel, dim3(blocks_for(n)), dim3(kRblBlock), 0, s, w.cell, n, w.start, w.fill,
                      w.idx);
   hipLaunchKernelGGL(rbl_segment_sort_kernel, dim3(blocks_for(nc)), dim3(kRblBlock), 0, s, w.start, nc, w.idx);
-  hipLaunchKernelGGL(rbl_gather_kernel, dim3(blocks_for(n)), dim3(kRblBlock), 0, s, x, y, z, q, eps, sig, n, seed,
-                     step, w);
+  hipLaunchKernelGGL(rbl_gather_kernel, dim3(blocks_for(n)), dim3(kRblBlock), 0, s, x, y, z, q, eps, sig, n, prm.L,
+                     seed, step, w);
   RblArgs a;
   a.n = n;
   a.ncell = nc;
@@ -833,6 +912,8 @@ rbe_status rbl_short_force(const rbl_plan* p, const double* x, const double* y, 
   a.tsap = 2.0 * std::sqrt(prm.alpha / kRblPi);
   a.rc2 = prm.r_c * prm.r_c;
   a.rs2 = prm.r_s * prm.r_s;
+  fixed_point_band(prm.r_c, prm.L, a.rc2lo, a.rc2hi);
+  fixed_point_band(prm.r_s, prm.L, a.rs2lo, a.rs2hi);
   hipLaunchKernelGGL(rbl_select_kernel, dim3((unsigned)(8 * a.nblk8)), dim3(kRblBlock), 0, s, w, a, g);
   const int64_t nbp = (n + kRblBlock - 1) / kRblBlock;
   hipLaunchKernelGGL(rbl_pair_kernel, dim3((unsigned)(8 * ((nbp + 7) / 8))), dim3(kRblBlock), 0, s, w, a, F, ns);
