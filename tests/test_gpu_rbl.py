@@ -41,7 +41,7 @@ CASES = [
     (250, 0.01, 0.06, 6.0, 12.0, 30, False),     # L = 29.2: 4 cells per axis, the stencil wraps
     (1500, 0.01, 0.06, 6.0, 12.0, 4000, False),  # batch larger than every shell: exact force
     (2500, 0.3, 0.3, 2.5, 5.0, 10, True),        # denser: about 5 particles per cell
-    (2000, 1.0, 0.3, 2.5, 5.0, 20, True),        # 16 per cell, stencil of 2000 > 1024 positions
+    (2000, 1.0, 0.3, 2.5, 5.0, 20, True),        # 16 per cell, stencils of 2000 positions
 ]
 
 
