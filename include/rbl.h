@@ -32,11 +32,13 @@
  * F[d N + i]; all arithmetic is FP64.  Scratch lives in a caller workspace of
  * rbl_plan_workspace_bytes() bytes, 256-byte aligned; work is enqueued on `stream`
  * without synchronisation.  Results are bitwise reproducible for the same inputs.
+ * Positions may lie outside [0, L) (they are wrapped); a non-finite position gives NaN
+ * forces, which the momentum correction carries to every particle.
  *
  * Work split: the fast path holds a cell's stencil of up to `stencil_positions` particles
  * in on-chip memory and up to `pairs_per_particle` core and batch pairs per particle in the
  * workspace (rbl_plan_capacity; sized from the mean density N / L^3 with a wide Poisson
- * allowance).  Particles beyond either take a slower path with the same result; the sum
+ * allowance, at most 4096).  Particles beyond either take a slower path with the same result; the sum
  * order of a particle's pairs differs between the two, by rounding only.
  */
 #ifndef RBL_H

@@ -74,10 +74,13 @@ struct RblWs {
   double* corr;      // 3
 };
 
-// Cell coordinate of a position along one axis: min(floor(frac(x / L) nc), nc - 1).
+// Cell coordinate of a position along one axis: min(floor(frac(x / L) nc), nc - 1).  A
+// non-finite coordinate gets cell 0 (its forces come out NaN and spread to every particle
+// through the momentum correction).
 __device__ inline int32_t cell_coord(double x, double L, int32_t nc) {
   const double s = x / L;
-  const double f = s - floor(s);
+  double f = s - floor(s);
+  if (!(f >= 0.0 && f < 1.0)) f = 0.0;
   const int32_t c = (int32_t)floor(f * (double)nc);
   return c < nc - 1 ? c : nc - 1;
 }
@@ -195,10 +198,11 @@ __global__ __launch_bounds__(kRblBlock) void rbl_segment_sort_kernel(const int32
   }
 }
 
-// floor(frac(x / L) 2^32), below 2^32.
+// floor(frac(x / L) 2^32), below 2^32 (0 for a non-finite coordinate).
 __device__ inline uint32_t fixed_coord(double x, double L) {
   const double s = x / L;
   const double v = (s - floor(s)) * 4294967296.0;
+  if (!(v >= 0.0)) return 0u;
   return v < 4294967295.0 ? (uint32_t)v : 0xffffffffu;
 }
 
@@ -281,6 +285,7 @@ static_assert(kListCap / 64 <= 32, "one bit per chunk in a 32-bit word");
 constexpr int kTgtGroup = 4;                // targets classified together
 constexpr int kFallbackBlocks = 512;
 constexpr int kCorrBlocks = 256;
+constexpr int kMaxPairSlots = 4096;         // pair slots per particle at most
 
 struct RblArgs {
   int64_t n, ncell;
@@ -572,6 +577,7 @@ __global__ __launch_bounds__(kRblBlock) void rbl_pair_kernel(RblWs w, RblArgs a,
     ay += wt * py;
     az += wt * pz;
   }
+  if (!isfinite(me.x + me.y + me.z)) ax = ay = az = __builtin_nan("");
   F[i] = ax;
   F[a.n + i] = ay;
   F[2 * a.n + i] = az;
@@ -685,6 +691,7 @@ __global__ __launch_bounds__(kRblBlock) void rbl_fallback_kernel(RblWs w, RblArg
       ay += __shfl_xor(ay, o, 64);
       az += __shfl_xor(az, o, 64);
     }
+    if (!isfinite(me.x + me.y + me.z)) ax = ay = az = __builtin_nan("");
     if (lane == 0) {
       F[i] = ax;
       F[a.n + i] = ay;
@@ -754,7 +761,7 @@ int32_t pair_slots(const rbl_params& q) {
   const double vs = 4.0 / 3.0 * kRblPi * q.r_s * q.r_s * q.r_s - vc;
   auto allow = [](double m) { return m + 6.0 * std::sqrt(m) + 16.0; };
   const double k = std::ceil(allow(dens * vc) + std::min((double)q.p, allow(dens * vs)));
-  return (int32_t)std::min(k, 65536.0);
+  return (int32_t)std::min(k, (double)kMaxPairSlots);
 }
 
 // The band around R^2 (fixed-point units u = L / 2^32) outside which the FP32 estimate f2 of

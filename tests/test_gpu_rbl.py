@@ -90,6 +90,30 @@ def test_rbl_parity_crowded():
     plan.close()
 
 
+def test_rbl_non_finite_position():
+    """A NaN or infinite coordinate is placed in cell 0 and gives NaN forces, which the
+    momentum correction carries to every particle; positions outside [0, L) are wrapped."""
+    s = ri.primitive_electrolyte(1500, 0.01, 77)
+    for bad in (float("nan"), float("inf")):
+        x = s.x.copy()
+        x[5] = bad
+        plan = RBLPlan(s.n, s.L, 0.06, 6.0, 12.0, 30, device=dev())
+        X = [to_dev(a) for a in (x, s.y, s.z, s.q, s.eps, s.sig)]
+        F, ns = plan.short_force(*X, seed=1, step=0)
+        torch.cuda.synchronize()
+        assert torch.isnan(F).all()
+        plan.close()
+    # shifted by whole periods: the same forces up to rounding
+    plan = RBLPlan(s.n, s.L, 0.06, 6.0, 12.0, 30, device=dev())
+    F0, n0 = plan.short_force(*[to_dev(a) for a in (s.x, s.y, s.z, s.q, s.eps, s.sig)], seed=1, step=0)
+    F1, n1 = plan.short_force(*[to_dev(a) for a in (s.x + 3 * s.L, s.y - 2 * s.L, s.z, s.q, s.eps, s.sig)],
+                              seed=1, step=0)
+    torch.cuda.synchronize()
+    assert torch.equal(n0, n1)
+    assert force_err(F1.cpu().numpy(), F0.cpu().numpy()) < 1e-12
+    plan.close()
+
+
 def test_rbl_repeatable_and_step_dependent():
     s = ri.primitive_electrolyte(3000, 0.01, 12)
     plan = RBLPlan(s.n, s.L, 0.06, 6.0, 12.0, 30, device=dev())
