@@ -182,7 +182,7 @@ def main():
         log("batched done")
         extra.update(bench_virial(torch, Plan, Batch, X, s, alpha, P, args.steps))
         log("virial done")
-        extra.update(bench_rbl(torch, ri, dev, max(5, args.steps // 5)))
+        extra.update(bench_rbl(torch, ri, dev, max(5, args.steps // 5), with_cpu=not args.no_cpu))
         log("rbl done")
 
     f32, f64 = res["fp32"], res["fp64"]
@@ -401,10 +401,13 @@ def errors_10M(torch, ri, Plan, Batch, dev):
     return out
 
 
-def bench_rbl(torch, ri, dev, steps):
+def bench_rbl(torch, ri, dev, steps, with_cpu=True):
     """RBL short-range force (cell list, core sum, shell batch, momentum correction) on the
     paper's primitive electrolyte at 0.01 particles / sigma^3, 1M particles, r_c = 6, r_s = 12,
-    alpha = 0.06, p = 30 and 100: whole evaluations back to back."""
+    alpha = 0.06, p = 30 and 100: whole evaluations back to back.  With with_cpu, the FP64
+    oracle's brute-force raw forces of 2,000 sampled particles (p = 30, median of 3) are timed
+    beside it and compared with the GPU's (raw-force differences F_i - F_0, which the momentum
+    correction leaves unchanged, and N_s)."""
     from paper_2407_09315_amd import RBLPlan
     s = ri.primitive_electrolyte(1_000_000, 0.01, 1006)
     X = [torch.tensor(a, dtype=torch.float64, device=dev) for a in (s.x, s.y, s.z, s.q, s.eps, s.sig)]
@@ -420,9 +423,35 @@ def bench_rbl(torch, ri, dev, steps):
             plan.short_force(*X, seed=1, step=k, F=F, ns=ns)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
-        out[f"rbl_short_force_electrolyte_1M_p{p}"] = {
-            "ms_per_evaluation": round(dt * 1e3, 4), "N": s.n, "L": round(s.L, 4), "r_c": 6.0, "r_s": 12.0, "p": p,
-            "mean_shell_size": round(float(ns.double().mean()), 2), "grid": plan.grid()}
+        key = f"rbl_short_force_electrolyte_1M_p{p}"
+        out[key] = {
+            "ms_per_evaluation": round(dt * 1e3, 4), "particles_per_s": round(s.n / dt, 1), "N": s.n,
+            "L": round(s.L, 4), "r_c": 6.0, "r_s": 12.0, "p": p,
+            "mean_shell_size": round(float(ns.double().mean()), 2), "grid": plan.grid(),
+            "pair_slots_per_particle": plan.capacity()[0]}
+        if with_cpu and p == 30:
+            import oracle
+            seed, step = 1, steps - 1   # the last timed evaluation's batch
+            sel = np.concatenate([[0], np.sort(np.random.default_rng(11).choice(np.arange(1, s.n), 1999,
+                                                                                 replace=False))])
+            u = oracle.rbl_offsets(seed, step, sel)
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                raw, ns_ref = oracle.rbl_raw_subset(s.x, s.y, s.z, s.q, s.eps, s.sig, s.L, 0.06, 6.0, 12.0, p, sel, u)
+                ts.append(time.perf_counter() - t0)
+            Fg = F.cpu().numpy()[:, sel]
+            d_gpu, d_ref = Fg - Fg[:, :1], raw - raw[:, :1]
+            rms = float(np.sqrt(np.mean(np.sum(raw ** 2, axis=0))))
+            t_cpu = float(np.median(ts))
+            out[key]["cpu_baseline"] = {
+                "value": round(len(sel) / t_cpu, 1), "unit": "particles/s", "cores": oracle.num_threads(),
+                "kind": "oracle",
+                "sample": f"raw RBL forces of {len(sel)} sampled particles of the same system (brute force over "
+                          f"all N in the oracle), median of 3: {t_cpu:.3f} s"}
+            out[key]["error_vs_oracle_sample"] = {
+                "n_s_equal": bool(np.array_equal(ns.cpu().numpy()[sel], ns_ref)),
+                "raw_force_difference_max_over_rms": float(np.max(np.sqrt(np.sum((d_gpu - d_ref) ** 2, axis=0))) / rms)}
         plan.close()
     return out
 
