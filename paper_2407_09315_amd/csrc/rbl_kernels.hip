@@ -8,9 +8,10 @@
 //             segment sorted by particle index, so the order is deterministic;
 //   gather  : positions, charges and LJ parameters copied into cell order, and every
 //             particle's batch offset u_i drawn;
-//   select  : one wave per cell classifies the cell's stencil against its particles (core
-//             and shell ballot masks) and writes every particle's pairs -- the core and the
-//             batch -- into a slot of Q entries;
+//   select  : one wave per cell classifies the cell's stencil against its particles (FP32
+//             distances from fixed-point coordinates, FP64 inside a band around the
+//             cutoffs) and writes every particle's pairs -- the core and the batch -- into
+//             a slot of Q entries;
 //   pairs   : one lane per particle adds its slot's pair forces in order;
 //   fallback: particles whose stencil or pair count exceeds what the selection holds are
 //             done one wave each, classifying the stencil window by window;
