@@ -4,8 +4,9 @@
     electrolyte at the paper's density with p = 30 and 100, unequal LJ parameters, a
     particle count off the block size, a box whose stencil wraps, a batch larger than
     every shell (the exact truncated force), a dense box whose cells hold more than one
-    group of targets and whose stencil is streamed in windows, and a packed cluster whose
-    particles have more pairs than the fast path's slots;
+    group of targets and whose stencil is streamed in windows, r_c = r_s (no shell), 50
+    particles with p = 1, and a packed cluster whose particles have more pairs than the fast
+    path's slots;
   * the 1M-particle benchmark system: N_s exact and the raw force differences F_i - F_0 of
     sampled particles (the momentum correction is one vector for all) against the oracle's
     brute-force raw forces of those particles, and sum_i F_i = 0;
@@ -42,6 +43,8 @@ CASES = [
     (1500, 0.01, 0.06, 6.0, 12.0, 4000, False),  # batch larger than every shell: exact force
     (2500, 0.3, 0.3, 2.5, 5.0, 10, True),        # denser: about 5 particles per cell
     (2000, 1.0, 0.3, 2.5, 5.0, 20, True),        # 16 per cell, stencils of 2000 positions
+    (2000, 0.01, 0.06, 8.0, 8.0, 30, False),     # r_c = r_s: the two bands coincide, no shell
+    (50, 0.01, 0.1, 3.0, 8.0, 1, True),          # 50 particles, p = 1, the stencil wraps
 ]
 
 
