@@ -298,6 +298,9 @@ struct RblArgs {
   float rc2lo, rc2hi, rs2lo, rs2hi;
 };
 
+// The lanes of the wave whose p is true (a comparison straight into a lane mask).
+__device__ inline uint64_t wave_mask(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
 __device__ inline int32_t lanes_below(uint64_t m) {
   return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -436,16 +439,18 @@ __global__ __launch_bounds__(kRblBlock) void rbl_select_kernel(RblWs w, RblArgs 
           const float fdy = (float)(int32_t)(tf[k].y - fo.y);
           const float fdz = (float)(int32_t)(tf[k].z - fo.z);
           const float f2 = fdx * fdx + fdy * fdy + fdz * fdz;
+          // bitwise, not short-circuit: straight-line lane masks
           const bool v = u >= 0;
           const bool near = f2 < a.rc2lo;
-          const bool shell = v && f2 > a.rc2hi && f2 < a.rs2lo;
-          const bool core = v && near && u != g0 + k;
-          const bool amb = v && !near && !shell && !(f2 > a.rs2hi);
+          const bool mid = (f2 > a.rc2hi) & (f2 < a.rs2lo);
+          const bool shell = v & mid;
+          const bool core = v & near & (u != g0 + k);
+          const bool amb = v & !near & !mid & !(f2 > a.rs2hi);
           cb[k] |= core ? bit : 0u;
           sb[k] |= shell ? bit : 0u;
-          nsk[k] += __popcll(__ballot(shell));
-          nck[k] += __popcll(__ballot(core));
-          ac[k] |= __ballot(amb) != 0 ? bit : 0u;
+          nsk[k] += __popcll(wave_mask(shell));
+          nck[k] += __popcll(wave_mask(core));
+          ac[k] |= wave_mask(amb) != 0 ? bit : 0u;
         }
       }
     }
@@ -491,8 +496,8 @@ __global__ __launch_bounds__(kRblBlock) void rbl_select_kernel(RblWs w, RblArgs 
           }
           cbits |= core ? (1u << c) : 0u;
           sbits |= shell ? (1u << c) : 0u;
-          ns += __popcll(__ballot(shell));
-          ncore += __popcll(__ballot(core));
+          ns += __popcll(wave_mask(shell));
+          ncore += __popcll(wave_mask(core));
         }
       }
       const bool sub = ns > a.p;
@@ -512,10 +517,10 @@ __global__ __launch_bounds__(kRblBlock) void rbl_select_kernel(RblWs w, RblArgs 
       int32_t pos0 = 0, rank0 = 0;
       for (int32_t c = 0; c < C; ++c) {
         const bool shell = (sbits >> c) & 1;
-        const uint64_t sm = __ballot(shell);
+        const uint64_t sm = wave_mask(shell);
         bool use = (cbits >> c) & 1;
         if (shell) use = !sub || mark[rank0 + lanes_below(sm)] != 0;
-        const uint64_t U = __ballot(use);
+        const uint64_t U = wave_mask(use);
         if (use) out[pos0 + lanes_below(U)] = (uint32_t)list[c * 64 + lane] | (shell ? 0x80000000u : 0u);
         pos0 += __popcll(U);
         rank0 += __popcll(sm);
@@ -627,7 +632,7 @@ __global__ __launch_bounds__(kRblBlock) void rbl_fallback_kernel(RblWs w, RblArg
       }
     };
     int32_t ns = 0;
-    classified([&](int32_t, bool, bool shell) { ns += __popcll(__ballot(shell)); });
+    classified([&](int32_t, bool, bool shell) { ns += __popcll(wave_mask(shell)); });
     const bool sub = ns > a.p;
     const double uoff = w.ru[t];
     const double wgt = sub ? (double)ns / (double)a.p : 1.0;
@@ -666,10 +671,10 @@ __global__ __launch_bounds__(kRblBlock) void rbl_fallback_kernel(RblWs w, RblArg
     };
     int32_t qn = 0, rank0 = 0;
     classified([&](int32_t u, bool core, bool shell) {
-      const uint64_t M = __ballot(shell);
+      const uint64_t M = wave_mask(shell);
       const bool use = core || (shell && (!sub || in_batch(rank0 + lanes_below(M))));
       rank0 += __popcll(M);
-      const uint64_t U = __ballot(use);
+      const uint64_t U = wave_mask(use);
       const int32_t cnt = __popcll(U);
       if (cnt == 0) return;
       const int32_t pos = qn + lanes_below(U);
