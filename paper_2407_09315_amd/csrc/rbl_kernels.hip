@@ -86,6 +86,17 @@ __device__ inline int32_t cell_coord(double x, double L, int32_t nc) {
   return c < nc - 1 ? c : nc - 1;
 }
 
+// Memory order of the cells: z runs are contiguous, and the nc^2 runs are laid out in tiles of
+// 8 x 8 (x, y) runs, x-major over the tiles and within a tile, so that a contiguous range of
+// cells (and of particles in cell order) is compact in space.  The rank of run (x, y):
+// slabs of 8 x values before x hold 8 nc runs each, the tiles before y in x's slab hold
+// 8 wx runs each (wx: the slab's width, 8 or less at the end), then x-major in the tile.
+__host__ __device__ inline int32_t run_rank(int32_t x, int32_t y, int32_t nc) {
+  const int32_t tx = x >> 3, ty = y >> 3;
+  const int32_t wx = min(8, nc - (tx << 3)), wy = min(8, nc - (ty << 3));
+  return (tx << 3) * nc + (ty << 3) * wx + (x & 7) * wy + (y & 7);
+}
+
 __global__ __launch_bounds__(kRblBlock) void rbl_zero_kernel(int32_t* __restrict__ a, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kRblBlock + threadIdx.x;
   if (i < n) a[i] = 0;
@@ -98,7 +109,7 @@ __global__ __launch_bounds__(kRblBlock) void rbl_cell_kernel(const double* __res
                                                              int32_t* __restrict__ count) {
   const int64_t i = (int64_t)blockIdx.x * kRblBlock + threadIdx.x;
   if (i >= n) return;
-  const int32_t c = (cell_coord(x[i], L, nc) * nc + cell_coord(y[i], L, nc)) * nc + cell_coord(z[i], L, nc);
+  const int32_t c = run_rank(cell_coord(x[i], L, nc), cell_coord(y[i], L, nc), nc) * nc + cell_coord(z[i], L, nc);
   cell[i] = c;
   atomicAdd(&count[c], 1);
 }
@@ -269,7 +280,7 @@ __device__ inline void pair_force_add(double qi, double qj, double rei, double r
 // c mod nc for c in [-nc, 2 nc): stencil offsets stay within one period.
 __device__ inline int32_t wrap_cell(int32_t c, int32_t nc) { return c < 0 ? c + nc : (c >= nc ? c - nc : c); }
 
-// Cell coordinates of cell index c = (cx nc + cy) nc + cz, through products with 1 / nc^2
+// Coordinates of the cell with x-major ordinal c = (cx nc + cy) nc + cz, through products with 1 / nc^2
 // and 1 / nc in FP64: the quotients' fractional parts are at least 0.5 / nc^2 away from an
 // integer, far beyond the rounding.
 __device__ inline void cell_coords(int32_t c, const RblGrid& g, int32_t& cx, int32_t& cy, int32_t& cz) {
@@ -331,7 +342,7 @@ __device__ int32_t fill_stencil_window(const RblWs& w, const RblGrid& g, int32_t
       // row / span through 1 / span in FP32: (row + 1/2) / span is at least 1 / (2 span)
       // from an integer, and span^2 < 2^19
       const int32_t a = (int32_t)(((float)row + 0.5f) * g.inv_span), b = row - a * span;
-      const int32_t base = (wrap_cell(cx + o0 + a, nc) * nc + wrap_cell(cy + o0 + b, nc)) * nc;
+      const int32_t base = run_rank(wrap_cell(cx + o0 + a, nc), wrap_cell(cy + o0 + b, nc), nc) * nc;
       const int32_t c0 = piece == 0 ? z0 : 0;
       const int32_t c1 = piece == 0 ? min(z0 + span, nc) : z0 + span - nc;
       sb = w.range[base + c0].x;
@@ -384,14 +395,15 @@ __global__ __launch_bounds__(kRblBlock) void rbl_select_kernel(RblWs w, RblArgs 
   if (blk >= a.nblk) return;
   const int32_t lane = (int32_t)(threadIdx.x & 63);
   const int32_t wv = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
-  const int32_t cidx = blk * kRblWaves + wv;
-  if (cidx >= a.ncell) return;
-  const int2 own = w.range[cidx];   // in flight with the stencil's ranges
+  // waves take the cells in x-major order of their coordinates
+  const int32_t ord = blk * kRblWaves + wv;
+  if (ord >= a.ncell) return;
+  int32_t cx, cy, cz;
+  cell_coords(ord, g, cx, cy, cz);
+  const int2 own = w.range[run_rank(cx, cy, g.nc) * g.nc + cz];   // in flight with the stencil's ranges
   int32_t* list = list_[wv];
   uint8_t* mark = reinterpret_cast<uint8_t*>(mark_[wv]);
   mark_[wv][lane] = 0;
-  int32_t cx, cy, cz;
-  cell_coords(cidx, g, cx, cy, cz);
   const int32_t T = fill_stencil_window(w, g, cx, cy, cz, 0, list, lane);
   const int32_t t0 = __builtin_amdgcn_readfirstlane(own.x), t1 = __builtin_amdgcn_readfirstlane(own.y);
   if (t1 <= t0) return;
@@ -609,10 +621,9 @@ __global__ __launch_bounds__(kRblBlock) void rbl_fallback_kernel(RblWs w, RblArg
   for (int32_t s = (int32_t)blockIdx.x * kRblWaves + wv; s < nfb; s += (int32_t)gridDim.x * kRblWaves) {
     const int32_t t = __builtin_amdgcn_readfirstlane(w.fb[s]);
     const int32_t i = w.idx[t];
-    int32_t cx, cy, cz;
-    cell_coords(w.cell[i], g, cx, cy, cz);
     const double4 me = w.rec[t].pq;
     const double2 mlj = w.rec[t].lj;
+    const int32_t cx = cell_coord(me.x, a.L, g.nc), cy = cell_coord(me.y, a.L, g.nc), cz = cell_coord(me.z, a.L, g.nc);
     wave_sync();
     const int32_t T = fill_stencil_window(w, g, cx, cy, cz, 0, list, lane);
     // fn(u, core, shell) for every stencil position, 64 at a time, window by window
@@ -736,6 +747,25 @@ __global__ __launch_bounds__(kRblBlock) void rbl_apply_kernel(const double* __re
   F[i] += corr[0];
   F[n + i] += corr[1];
   F[2 * n + i] += corr[2];
+}
+
+// Dynamic LDS for the pair kernel that leaves room for two of its blocks per CU.  Fewer
+// particles in flight keep their candidates' records in the L2: on the 1M electrolyte the
+// pass took 0.51 ms at two blocks per CU against 0.56 ms at the four its registers allow.
+// 0 when the device cannot be queried or would refuse the size (no cap then).
+size_t pair_kernel_lds() {
+  static size_t bytes = (size_t)-1;
+  if (bytes == (size_t)-1) {
+    int dev = 0, per_cu = 0, per_block = 0;
+    bytes = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
+        hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess) {
+      const size_t want = (size_t)per_cu / 3 + 1024;
+      if (per_cu > 0 && want <= (size_t)per_block) bytes = want;
+    }
+  }
+  return bytes;
 }
 
 unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>((n + kRblBlock - 1) / kRblBlock, 1); }
@@ -929,7 +959,8 @@ rbe_status rbl_short_force(const rbl_plan* p, const double* x, const double* y, 
   fixed_point_band(prm.r_s, prm.L, a.rs2lo, a.rs2hi);
   hipLaunchKernelGGL(rbl_select_kernel, dim3((unsigned)(8 * a.nblk8)), dim3(kRblBlock), 0, s, w, a, g);
   const int64_t nbp = (n + kRblBlock - 1) / kRblBlock;
-  hipLaunchKernelGGL(rbl_pair_kernel, dim3((unsigned)(8 * ((nbp + 7) / 8))), dim3(kRblBlock), 0, s, w, a, F, ns);
+  hipLaunchKernelGGL(rbl_pair_kernel, dim3((unsigned)(8 * ((nbp + 7) / 8))), dim3(kRblBlock), pair_kernel_lds(), s, w,
+                     a, F, ns);
   hipLaunchKernelGGL(rbl_fallback_kernel, dim3(kFallbackBlocks), dim3(kRblBlock), 0, s, w, a, g, F, ns);
   const int64_t per = (n + kCorrBlocks - 1) / kCorrBlocks;
   const int64_t nb1 = (n + per - 1) / per;
