@@ -312,6 +312,20 @@ struct RblArgs {
 // The lanes of the wave whose p is true (a comparison straight into a lane mask).
 __device__ inline uint64_t wave_mask(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// The sum of v over the 64 lanes, in every lane's hands.  Data-parallel-primitive moves: an
+// inclusive scan within each row of 16 lanes (shifts right by 1, 2, 4, 8, an empty source
+// giving 0), then row 0's total broadcast into rows 1 and 3 and lane 31's into rows 2 and 3,
+// so lane 63 holds the total.
+__device__ inline int32_t wave_sum(int32_t v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);   // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);   // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);   // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);   // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
 __device__ inline int32_t lanes_below(uint64_t m) {
   return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -419,10 +433,9 @@ __global__ __launch_bounds__(kRblBlock) void rbl_select_kernel(RblWs w, RblArgs 
   for (int32_t g0 = t0; g0 < t1; g0 += kTgtGroup) {
     const int32_t mg = min(kTgtGroup, t1 - g0);
     uint4 tf[kTgtGroup];
-    // bit c of cb[k] / sb[k]: this lane's candidate of chunk c is a core / shell member of
-    // target g0 + k; bit c of ac[k]: chunk c holds lanes left ambiguous for it
-    uint32_t cb[kTgtGroup], sb[kTgtGroup], ac[kTgtGroup];
-    int32_t nsk[kTgtGroup], nck[kTgtGroup];
+    // bit c of cb[k] / sb[k] / ab[k]: this lane's candidate of chunk c is a core / shell /
+    // ambiguous member of target g0 + k (the counts come from these bits afterwards)
+    uint32_t cb[kTgtGroup], sb[kTgtGroup], ab[kTgtGroup];
     // every load of the group is issued here: a wait for a load also waits for the stores
     // before it, and the slot writes below are many
     double ug[kTgtGroup];
@@ -430,8 +443,7 @@ __global__ __launch_bounds__(kRblBlock) void rbl_select_kernel(RblWs w, RblArgs 
     for (int k = 0; k < kTgtGroup; ++k) {
       tf[k] = w.rec[g0 + min(k, mg - 1)].fx;
       ug[k] = w.ru[g0 + min(k, mg - 1)];
-      cb[k] = sb[k] = ac[k] = 0;
-      nsk[k] = nck[k] = 0;
+      cb[k] = sb[k] = ab[k] = 0;
     }
     int32_t un = lane < T ? list[lane] : -1;
     uint4 fn = un >= 0 ? w.rec[un].fx : make_uint4(0u, 0u, 0u, 0u);
@@ -460,58 +472,37 @@ __global__ __launch_bounds__(kRblBlock) void rbl_select_kernel(RblWs w, RblArgs 
           const bool amb = v & !near & !mid & !(f2 > a.rs2hi);
           cb[k] |= core ? bit : 0u;
           sb[k] |= shell ? bit : 0u;
-          nsk[k] += __popcll(wave_mask(shell));
-          nck[k] += __popcll(wave_mask(core));
-          ac[k] |= wave_mask(amb) != 0 ? bit : 0u;
+          ab[k] |= amb ? bit : 0u;
         }
       }
     }
     for (int32_t k = 0; k < mg; ++k) {
       const int32_t t = g0 + k;
-      uint32_t cbits = 0, sbits = 0, ambc = 0;
-      int32_t ns = 0, ncore = 0;
+      uint32_t cbits = 0, sbits = 0, abits = 0;
       double uoff = 0.0;
 #pragma unroll
       for (int kk = 0; kk < kTgtGroup; ++kk) {
         if (kk == k) {
           cbits = cb[kk];
           sbits = sb[kk];
-          ambc = ac[kk];
-          ns = nsk[kk];
-          ncore = nck[kk];
+          abits = ab[kk];
           uoff = ug[kk];
         }
       }
-      if (ambc != 0) {
-        // the ambiguous lanes, with the FP64 distance of the definition
+      if (wave_mask(abits != 0) != 0) {
+        // the ambiguous lanes (rare), with the FP64 distance of the definition
         const double4 me = w.rec[t].pq;
-        const uint4 mf = w.rec[t].fx;
         for (int32_t c = 0; c < C; ++c) {
-          if (((ambc >> c) & 1) == 0) continue;
-          const int32_t f = c * 64 + lane;
-          const int32_t u = f < T ? list[f] : -1;
-          bool core = false, shell = false;
-          if (u >= 0) {
-            const uint4 fo = w.rec[u].fx;
-            const float fdx = (float)(int32_t)(mf.x - fo.x);
-            const float fdy = (float)(int32_t)(mf.y - fo.y);
-            const float fdz = (float)(int32_t)(mf.z - fo.z);
-            const float f2 = fdx * fdx + fdy * fdy + fdz * fdz;
-            const bool near = f2 < a.rc2lo;
-            const bool sh = f2 > a.rc2hi && f2 < a.rs2lo;
-            if (!near && !sh && !(f2 > a.rs2hi)) {
-              double dx, dy, dz;
-              const double r2 = separation(me.x, me.y, me.z, w.rec[u].pq, a.L, a.invL, dx, dy, dz);
-              core = r2 < a.rc2 && u != t;
-              shell = r2 >= a.rc2 && r2 <= a.rs2;
-            }
+          if ((abits >> c) & 1) {
+            const int32_t u = list[c * 64 + lane];
+            double dx, dy, dz;
+            const double r2 = separation(me.x, me.y, me.z, w.rec[u].pq, a.L, a.invL, dx, dy, dz);
+            cbits |= (r2 < a.rc2 && u != t) ? (1u << c) : 0u;
+            sbits |= (r2 >= a.rc2 && r2 <= a.rs2) ? (1u << c) : 0u;
           }
-          cbits |= core ? (1u << c) : 0u;
-          sbits |= shell ? (1u << c) : 0u;
-          ns += __popcll(wave_mask(shell));
-          ncore += __popcll(wave_mask(core));
         }
       }
+      const int32_t ns = wave_sum(__popc(sbits)), ncore = wave_sum(__popc(cbits));
       const bool sub = ns > a.p;
       const int32_t total = ncore + (sub ? a.p : ns);
       if (total > a.Q) {
