@@ -6,8 +6,8 @@
 //   cells   : cell of every particle, per-cell counts (atomic adds), exclusive scan into
 //             cell starts, scatter into cell order (atomic slots), then every cell's short
 //             segment sorted by particle index, so the order is deterministic;
-//   gather  : positions, charges and LJ parameters copied into cell order, and every
-//             particle's batch offset u_i drawn;
+//   gather  : positions, charges and LJ parameters read in particle order and written into
+//             cell order, and every particle's batch offset u_i drawn;
 //   select  : one wave per cell classifies the cell's stencil against its particles (FP32
 //             distances from fixed-point coordinates, FP64 inside a band around the
 //             cutoffs) and writes every particle's pairs -- the core and the batch -- into
@@ -61,7 +61,7 @@ struct RblWs {
   int32_t* fill;
   int32_t* start;    // ncell + 1
   int32_t* bsum;     // scan block sums
-  int32_t* cell;     // N, by particle index
+  int32_t* cell;     // N, by particle index: the cell, then (after the sort) the cell-order position
   int32_t* idx;      // N: particle index at each cell-order position
   RblRec* rec;       // N, in cell order
   int2* range;       // ncell: first and one-past-last cell-order position of each cell
@@ -193,9 +193,10 @@ __global__ __launch_bounds__(kRblBlock) void rbl_scatter_kernel(const int32_t* _
 }
 
 // Each cell's segment in ascending particle index (insertion sort: cells hold a few to a
-// few dozen particles).
+// few dozen particles), then every particle's cell-order position written by particle index
+// into pos.
 __global__ __launch_bounds__(kRblBlock) void rbl_segment_sort_kernel(const int32_t* __restrict__ start, int64_t ncell,
-                                                                     int32_t* __restrict__ idx) {
+                                                                     int32_t* __restrict__ idx, int32_t* __restrict__ pos) {
   const int64_t c = (int64_t)blockIdx.x * kRblBlock + threadIdx.x;
   if (c >= ncell) return;
   const int32_t b = start[c], e = start[c + 1];
@@ -208,6 +209,7 @@ __global__ __launch_bounds__(kRblBlock) void rbl_segment_sort_kernel(const int32
     }
     idx[j + 1] = v;
   }
+  for (int32_t k = b; k < e; ++k) pos[idx[k]] = k;
 }
 
 // floor(frac(x / L) 2^32), below 2^32 (0 for a non-finite coordinate).
@@ -223,9 +225,11 @@ __global__ __launch_bounds__(kRblBlock) void rbl_gather_kernel(const double* __r
                                                                const double* __restrict__ eps,
                                                                const double* __restrict__ sig, int64_t n, double L,
                                                                uint64_t seed, uint64_t step, RblWs w) {
-  const int64_t t = (int64_t)blockIdx.x * kRblBlock + threadIdx.x;
-  if (t >= n) return;
-  const int32_t i = w.idx[t];
+  // in particle order: the inputs are read in order and each record written to its
+  // cell-order position
+  const int64_t i = (int64_t)blockIdx.x * kRblBlock + threadIdx.x;
+  if (i >= n) return;
+  const int32_t t = w.cell[i];
   RblRec r;
   r.pq = make_double4(x[i], y[i], z[i], q[i]);
   r.lj = make_double2(sqrt(eps[i]), sig[i]);
@@ -929,7 +933,7 @@ rbe_status rbl_short_force(const rbl_plan* p, const double* x, const double* y, 
                      w.start, w.range, n);
   hipLaunchKernelGGL(rbl_scatter_kernel, dim3(blocks_for(n)), dim3(kRblBlock), 0, s, w.cell, n, w.start, w.fill,
                      w.idx);
-  hipLaunchKernelGGL(rbl_segment_sort_kernel, dim3(blocks_for(nc)), dim3(kRblBlock), 0, s, w.start, nc, w.idx);
+  hipLaunchKernelGGL(rbl_segment_sort_kernel, dim3(blocks_for(nc)), dim3(kRblBlock), 0, s, w.start, nc, w.idx, w.cell);
   hipLaunchKernelGGL(rbl_gather_kernel, dim3(blocks_for(n)), dim3(kRblBlock), 0, s, x, y, z, q, eps, sig, n, prm.L,
                      seed, step, w);
   RblArgs a;
