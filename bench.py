@@ -407,11 +407,15 @@ def bench_rbl(torch, ri, dev, steps, with_cpu=True):
     alpha = 0.06, p = 30 and 100: whole evaluations back to back.  With with_cpu, the FP64
     oracle's brute-force raw forces of 2,000 sampled particles (p = 30, median of 3) are timed
     beside it and compared with the GPU's (raw-force differences F_i - F_0, which the momentum
-    correction leaves unchanged, and N_s)."""
+    correction leaves unchanged, and N_s).  The selection and pair kernels are timed with events
+    the library records around them; each gets a roofline line against the FP64 vector peak (the
+    rate of unpacked FP32 too), its work counted from the definition: the stencil population
+    from the cell counts, the core and shell sizes from a periodic k-d tree."""
     from paper_2407_09315_amd import RBLPlan
     s = ri.primitive_electrolyte(1_000_000, 0.01, 1006)
     X = [torch.tensor(a, dtype=torch.float64, device=dev) for a in (s.x, s.y, s.z, s.q, s.eps, s.sig)]
     out = {}
+    counts = None
     for p in (30, 100):
         plan = RBLPlan(s.n, s.L, 0.06, 6.0, 12.0, p, device=dev)
         F, ns = plan.short_force(*X, seed=1, step=0)
@@ -423,12 +427,45 @@ def bench_rbl(torch, ri, dev, steps, with_cpu=True):
             plan.short_force(*X, seed=1, step=k, F=F, ns=ns)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
+        # the selection and pair kernels, with events recorded around them by the library
+        evs = []
+        for k in range(steps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            for e in ev:
+                e.record()
+            plan.set_timing_events(*ev)
+            plan.short_force(*X, seed=1, step=k, F=F, ns=ns)
+            evs.append(ev)
+        plan.set_timing_events()
+        torch.cuda.synchronize()
+        t_sel = float(np.mean([e[0].elapsed_time(e[1]) for e in evs])) * 1e-3
+        t_pair = float(np.mean([e[2].elapsed_time(e[3]) for e in evs])) * 1e-3
+        nc, R, span = plan.grid()
+        if counts is None:
+            counts = (stencil_population(s, nc, span),) + neighbour_counts(s, 6.0, 12.0)
+        T, core, shell = counts
+        pairs = float(core.sum() + np.minimum(shell, p).sum())
+        lines = {
+            "rbl_select_kernel": (t_sel, 8.0 * T * s.n,
+                                  "8 FP64 FLOP per (particle, stencil candidate) distance test; "
+                                  f"{T:.2f} candidates per particle"),
+            "rbl_pair_kernel": (t_pair, 42.0 * pairs,
+                                "42 FP64 FLOP per core or batch pair (distance 8, 1/r^2, r, 1/r 3, "
+                                "Lennard-Jones with the mixing rules 13, real-space Coulomb 12, "
+                                f"sum 6; erfc, exp, sqrt, divide as one each); {pairs / s.n:.2f} pairs per particle")}
+        roof = {k: {"bound": "alu", "kernel": k, "achieved": round(f / t / 1e12, 3), "peak": 78.6,
+                    "unit": "TFLOP/s", "frac": round(f / t / 78.6e12, 4), "traffic": None, "work": w,
+                    "kernel_ms": round(t * 1e3, 4)}
+                for k, (t, f, w) in lines.items()}
+        dom = max(roof, key=lambda k: roof[k]["kernel_ms"])
         key = f"rbl_short_force_electrolyte_1M_p{p}"
         out[key] = {
             "ms_per_evaluation": round(dt * 1e3, 4), "particles_per_s": round(s.n / dt, 1), "N": s.n,
             "L": round(s.L, 4), "r_c": 6.0, "r_s": 12.0, "p": p,
-            "mean_shell_size": round(float(ns.double().mean()), 2), "grid": plan.grid(),
-            "pair_slots_per_particle": plan.capacity()[0]}
+            "mean_shell_size": round(float(ns.double().mean()), 2), "grid": [nc, R, span],
+            "pair_slots_per_particle": plan.capacity()[0],
+            "select_kernel_ms": round(t_sel * 1e3, 4), "pair_kernel_ms": round(t_pair * 1e3, 4),
+            "roofline": roof[dom], "roofline_other": [roof[k] for k in roof if k != dom]}
         if with_cpu and p == 30:
             import oracle
             seed, step = 1, steps - 1   # the last timed evaluation's batch
@@ -454,6 +491,31 @@ def bench_rbl(torch, ri, dev, steps, with_cpu=True):
                 "raw_force_difference_max_over_rms": float(np.max(np.sqrt(np.sum((d_gpu - d_ref) ** 2, axis=0))) / rms)}
         plan.close()
     return out
+
+
+def stencil_population(s, nc, span):
+    """Mean over particles of the number of particles in their cell stencil (span^3 cells,
+    periodic), from the cell counts: sum over cells of n_c times its stencil's count, / N."""
+    cell = [np.minimum(np.floor((v / s.L - np.floor(v / s.L)) * nc).astype(np.int64), nc - 1) for v in (s.x, s.y, s.z)]
+    counts = np.bincount((cell[0] * nc + cell[1]) * nc + cell[2], minlength=nc ** 3).reshape(nc, nc, nc).astype(np.float64)
+    acc = counts
+    for axis in range(3):
+        offs = range(span) if span == nc else range(-(span // 2), span // 2 + 1)
+        acc = sum(np.roll(acc, o, axis=axis) for o in offs)
+    return float((counts * acc).sum() / s.n)
+
+
+def neighbour_counts(s, rc, rs):
+    """(core, shell) neighbour counts per particle, r < r_c and r_c <= r <= r_s under the minimum
+    image, from a periodic k-d tree (the work the pair kernel's definition implies)."""
+    from scipy.spatial import cKDTree
+    P = np.stack([s.x, s.y, s.z], 1)
+    P = P - np.floor(P / s.L) * s.L
+    P[P >= s.L] = 0.0
+    tree = cKDTree(P, boxsize=s.L)
+    c = tree.query_ball_point(P, rc, return_length=True, workers=8)
+    a = tree.query_ball_point(P, rs, return_length=True, workers=8)
+    return c - 1, a - c
 
 
 def bench_virial(torch, Plan, Batch, X, s, alpha, P, steps):

@@ -67,6 +67,11 @@ rbe_status rbl_plan_create(const rbl_params *params, rbl_plan **out);
 size_t rbl_plan_workspace_bytes(const rbl_plan *plan);
 /* The cell grid: cells per axis, stencil reach R (in cells) and cells per stencil axis. */
 rbe_status rbl_plan_grid(const rbl_plan *plan, int32_t *cells_per_axis, int32_t *reach, int32_t *stencil_span);
+/* Events (hipEvent_t, created and owned by the caller) that rbl_short_force records on its
+   stream just before and after the selection kernel and the pair kernel, for timing those two
+   kernels; NULL clears a slot.  RBE_EINVAL for a NULL plan. */
+rbe_status rbl_plan_set_timing_events(rbl_plan *plan, void *select_begin, void *select_end, void *pair_begin,
+                                      void *pair_end);
 /* The fast path's limits: pair slots per particle and stencil positions per cell. */
 rbe_status rbl_plan_capacity(const rbl_plan *plan, int32_t *pairs_per_particle, int32_t *stencil_positions);
 void rbl_plan_destroy(rbl_plan *plan);

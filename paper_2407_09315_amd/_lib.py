@@ -56,6 +56,7 @@ SIGNATURES = {
     "rbl_plan_workspace_bytes": (_SZ, [_VP]),
     "rbl_plan_grid": (_ST, [_VP, _VP, _VP, _VP]),
     "rbl_plan_capacity": (_ST, [_VP, _VP, _VP]),
+    "rbl_plan_set_timing_events": (_ST, [_VP] * 5),
     "rbl_plan_destroy": (None, [_VP]),
     "rbl_short_force": (_ST, [_VP] * 7 + [_U64, _U64] + [_VP] * 4),
     "rbe_status_string": (ctypes.c_char_p, [_ST]),

@@ -779,6 +779,7 @@ struct rbl_plan {
   int32_t Q = 0;         // pair slots per particle
   size_t off[17] = {};
   size_t bytes = 0;
+  hipEvent_t ev[4] = {};  // caller's events around the select and pair kernels (optional)
 };
 
 namespace {
@@ -904,6 +905,16 @@ rbe_status rbl_plan_capacity(const rbl_plan* p, int32_t* pairs_per_particle, int
   return RBE_OK;
 }
 
+rbe_status rbl_plan_set_timing_events(rbl_plan* p, void* select_begin, void* select_end, void* pair_begin,
+                                      void* pair_end) {
+  if (p == nullptr) return fail(RBE_EINVAL, "plan is NULL");
+  p->ev[0] = static_cast<hipEvent_t>(select_begin);
+  p->ev[1] = static_cast<hipEvent_t>(select_end);
+  p->ev[2] = static_cast<hipEvent_t>(pair_begin);
+  p->ev[3] = static_cast<hipEvent_t>(pair_end);
+  return RBE_OK;
+}
+
 void rbl_plan_destroy(rbl_plan* p) { delete p; }
 
 rbe_status rbl_short_force(const rbl_plan* p, const double* x, const double* y, const double* z, const double* q,
@@ -952,10 +963,14 @@ rbe_status rbl_short_force(const rbl_plan* p, const double* x, const double* y, 
   a.rs2 = prm.r_s * prm.r_s;
   fixed_point_band(prm.r_c, prm.L, a.rc2lo, a.rc2hi);
   fixed_point_band(prm.r_s, prm.L, a.rs2lo, a.rs2hi);
+  if (p->ev[0] != nullptr) (void)hipEventRecord(p->ev[0], s);
   hipLaunchKernelGGL(rbl_select_kernel, dim3((unsigned)(8 * a.nblk8)), dim3(kRblBlock), 0, s, w, a, g);
+  if (p->ev[1] != nullptr) (void)hipEventRecord(p->ev[1], s);
   const int64_t nbp = (n + kRblBlock - 1) / kRblBlock;
+  if (p->ev[2] != nullptr) (void)hipEventRecord(p->ev[2], s);
   hipLaunchKernelGGL(rbl_pair_kernel, dim3((unsigned)(8 * ((nbp + 7) / 8))), dim3(kRblBlock), pair_kernel_lds(), s, w,
                      a, F, ns);
+  if (p->ev[3] != nullptr) (void)hipEventRecord(p->ev[3], s);
   hipLaunchKernelGGL(rbl_fallback_kernel, dim3(kFallbackBlocks), dim3(kRblBlock), 0, s, w, a, g, F, ns);
   const int64_t per = (n + kCorrBlocks - 1) / kCorrBlocks;
   const int64_t nb1 = (n + per - 1) / per;

@@ -481,6 +481,14 @@ class RBLPlan:
         check(self.lib.rbl_plan_grid(self.handle, *[ctypes.byref(a) for a in v]), "rbl_plan_grid")
         return tuple(a.value for a in v)
 
+    def set_timing_events(self, select_begin=None, select_end=None, pair_begin=None, pair_end=None):
+        """Record torch.cuda.Events (already recorded once, so their handles exist) around the
+        selection and pair kernels of later short_force calls."""
+        evs = (select_begin, select_end, pair_begin, pair_end)
+        h = [ctypes.c_void_p(e.cuda_event) if e is not None else ctypes.c_void_p(0) for e in evs]
+        check(self.lib.rbl_plan_set_timing_events(self.handle, *h), "rbl_plan_set_timing_events")
+        self._events = tuple(e for e in evs if e is not None)
+
     def capacity(self):
         """(pair slots per particle, stencil positions per cell) of the fast path."""
         v = [ctypes.c_int32() for _ in range(2)]

@@ -267,6 +267,8 @@ def test_rbl_plan_validation_and_grid():
     assert c[0].value == math.ceil(allow(mc) + min(10, allow(ms))) and c[1].value == 512
     assert lib.rbl_plan_workspace_bytes(h) >= 1000 * c[0].value * 4
     assert lib.rbl_plan_capacity(None, *[ctypes.byref(a) for a in c]) == _lib.RBE_EINVAL
+    assert lib.rbl_plan_set_timing_events(h, None, None, None, None) == 0      # clears, records nothing
+    assert lib.rbl_plan_set_timing_events(None, None, None, None, None) == _lib.RBE_EINVAL
     lib.rbl_plan_destroy(h)
     st, h = _rbl(L=21.0, rc=5.0, rs=10.0)                # 4 cells per axis: the stencil wraps
     assert st == 0
