@@ -66,7 +66,7 @@ struct RblWs {
   RblRec* rec;       // N, in cell order
   int2* range;       // ncell: first and one-past-last cell-order position of each cell
   double* ru;        // N, in cell order: the particle's batch offset u_i
-  uint32_t* slot;    // N x Q pair entries, in cell order
+  uint32_t* slot;    // Q pair entries per particle, interleaved (slot_index)
   int32_t* cnt;      // N, in cell order: pairs in the slot, -1 for the fallback
   int32_t* tns;      // N, in cell order: N_s
   int32_t* fb;       // N: cell-order positions left to the fallback
@@ -279,6 +279,13 @@ __device__ inline void pair_force_add(double qi, double qj, double rei, double r
   fx += g * dx;
   fy += g * dy;
   fz += g * dz;
+}
+
+// Position of pair entry j of the particle at cell-order position t.  The slots of 64
+// consecutive particles are interleaved in groups of 4 entries, so the pair pass reads its
+// 64 lanes' next 4 entries as one contiguous kilobyte, 16 B per lane (Q is a multiple of 4).
+__device__ inline int64_t slot_index(int64_t t, int32_t Q, int32_t j) {
+  return (t >> 6) * 64 * (int64_t)Q + (t & 63) * 4 + (int64_t)(j >> 2) * 256 + (j & 3);
 }
 
 // c mod nc for c in [-nc, 2 nc): stencil offsets stay within one period.
@@ -520,7 +527,6 @@ __global__ __launch_bounds__(kRblBlock) void rbl_select_kernel(RblWs w, RblArgs 
         for (int32_t b = lane; b < a.p; b += 64) mark[batch_pos(b, uoff, ns, a.p)] = 1;
         wave_sync();
       }
-      uint32_t* out = w.slot + (int64_t)t * a.Q;
       int32_t pos0 = 0, rank0 = 0;
       for (int32_t c = 0; c < C; ++c) {
         const bool shell = (sbits >> c) & 1;
@@ -528,7 +534,7 @@ __global__ __launch_bounds__(kRblBlock) void rbl_select_kernel(RblWs w, RblArgs 
         bool use = (cbits >> c) & 1;
         if (shell) use = !sub || mark[rank0 + lanes_below(sm)] != 0;
         const uint64_t U = wave_mask(use);
-        if (use) out[pos0 + lanes_below(U)] = (uint32_t)list[c * 64 + lane] | (shell ? 0x80000000u : 0u);
+        if (use) w.slot[slot_index(t, a.Q, pos0 + lanes_below(U))] = (uint32_t)list[c * 64 + lane] | (shell ? 0x80000000u : 0u);
         pos0 += __popcll(U);
         rank0 += __popcll(sm);
       }
@@ -559,27 +565,34 @@ __global__ __launch_bounds__(kRblBlock) void rbl_pair_kernel(RblWs w, RblArgs a,
   const int32_t i = (int32_t)w.rec[t].fx.w;
   const int32_t ns = w.tns[t];
   const double wgt = ns > a.p ? (double)ns / (double)a.p : 1.0;
-  const uint32_t* e = w.slot + t * a.Q;
+  // this particle's groups of 4 entries, 64 groups (1 KB) apart
+  const uint4* e = reinterpret_cast<const uint4*>(w.slot + slot_index(t, a.Q, 0));
   double ax = 0.0, ay = 0.0, az = 0.0;
-  // software pipeline: pair j + 1's data and pair j + 2's entry are in flight while pair j
-  // is evaluated
-  uint32_t en = cnt > 0 ? e[0] : 0u;
+  // software pipeline: pair j + 1's data and the next group of entries are in flight while
+  // pair j is evaluated
+  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+  uint4 cur = cnt > 0 ? e[0] : z4;
+  uint4 nxt = cnt > 4 ? e[64] : z4;
+  uint32_t en = cur.x;
   double4 on = make_double4(0.0, 0.0, 0.0, 0.0);
   double2 ljn = make_double2(0.0, 0.0);
   if (cnt > 0) {
     on = w.rec[en & 0x7fffffffu].pq;
     ljn = w.rec[en & 0x7fffffffu].lj;
   }
-  uint32_t enn = cnt > 1 ? e[1] : 0u;
   for (int32_t j = 0; j < cnt; ++j) {
     const uint32_t ej = en;
     const double4 o = on;
     const double2 olj = ljn;
     if (j + 1 < cnt) {
-      en = enn;
+      const int32_t k = (j + 1) & 3;   // the same on every lane
+      if (k == 0) {
+        cur = nxt;
+        if (j + 5 < cnt) nxt = e[((j + 5) >> 2) * 64];
+      }
+      en = k == 0 ? cur.x : k == 1 ? cur.y : k == 2 ? cur.z : cur.w;
       on = w.rec[en & 0x7fffffffu].pq;
       ljn = w.rec[en & 0x7fffffffu].lj;
-      if (j + 2 < cnt) enn = e[j + 2];
     }
     double dx, dy, dz;
     const double r2 = separation(me.x, me.y, me.z, o, a.L, a.invL, dx, dy, dz);
@@ -744,25 +757,6 @@ __global__ __launch_bounds__(kRblBlock) void rbl_apply_kernel(const double* __re
   F[2 * n + i] += corr[2];
 }
 
-// Dynamic LDS for the pair kernel that leaves room for two of its blocks per CU.  Fewer
-// particles in flight keep their candidates' records in the L2: on the 1M electrolyte the
-// pass took 0.51 ms at two blocks per CU against 0.56 ms at the four its registers allow.
-// 0 when the device cannot be queried or would refuse the size (no cap then).
-size_t pair_kernel_lds() {
-  static size_t bytes = (size_t)-1;
-  if (bytes == (size_t)-1) {
-    int dev = 0, per_cu = 0, per_block = 0;
-    bytes = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
-        hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess) {
-      const size_t want = (size_t)per_cu / 3 + 1024;
-      if (per_cu > 0 && want <= (size_t)per_block) bytes = want;
-    }
-  }
-  return bytes;
-}
-
 unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>((n + kRblBlock - 1) / kRblBlock, 1); }
 
 }  // namespace
@@ -793,7 +787,7 @@ int32_t pair_slots(const rbl_params& q) {
   const double vs = 4.0 / 3.0 * kRblPi * q.r_s * q.r_s * q.r_s - vc;
   auto allow = [](double m) { return m + 6.0 * std::sqrt(m) + 16.0; };
   const double k = std::ceil(allow(dens * vc) + std::min((double)q.p, allow(dens * vs)));
-  return (int32_t)std::min(k, (double)kMaxPairSlots);
+  return (int32_t)std::min(4.0 * std::ceil(k / 4.0), (double)kMaxPairSlots);
 }
 
 // The band around R^2 (fixed-point units u = L / 2^32) outside which the FP32 estimate f2 of
@@ -815,7 +809,7 @@ void rbl_layout(rbl_plan* p) {
       sizeof(int32_t) * nc,        sizeof(int32_t) * nc,           sizeof(int32_t) * (nc + 1),
       sizeof(int32_t) * (size_t)(p->nscan + 1), sizeof(int32_t) * n, sizeof(int32_t) * n,
       sizeof(RblRec) * n,          1,                              sizeof(int2) * nc,
-      sizeof(double) * n,          sizeof(uint32_t) * n * (size_t)p->Q, sizeof(int32_t) * n,
+      sizeof(double) * n,          sizeof(uint32_t) * 64 * ((n + 63) / 64) * (size_t)p->Q, sizeof(int32_t) * n,
       sizeof(int32_t) * n,         sizeof(int32_t) * n,            sizeof(int32_t),
       sizeof(double) * 3 * kCorrBlocks, sizeof(double) * 3};
   size_t o = 0;
@@ -968,8 +962,7 @@ rbe_status rbl_short_force(const rbl_plan* p, const double* x, const double* y, 
   if (p->ev[1] != nullptr) (void)hipEventRecord(p->ev[1], s);
   const int64_t nbp = (n + kRblBlock - 1) / kRblBlock;
   if (p->ev[2] != nullptr) (void)hipEventRecord(p->ev[2], s);
-  hipLaunchKernelGGL(rbl_pair_kernel, dim3((unsigned)(8 * ((nbp + 7) / 8))), dim3(kRblBlock), pair_kernel_lds(), s, w,
-                     a, F, ns);
+  hipLaunchKernelGGL(rbl_pair_kernel, dim3((unsigned)(8 * ((nbp + 7) / 8))), dim3(kRblBlock), 0, s, w, a, F, ns);
   if (p->ev[3] != nullptr) (void)hipEventRecord(p->ev[3], s);
   hipLaunchKernelGGL(rbl_fallback_kernel, dim3(kFallbackBlocks), dim3(kRblBlock), 0, s, w, a, g, F, ns);
   const int64_t per = (n + kCorrBlocks - 1) / kCorrBlocks;

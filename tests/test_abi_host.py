@@ -264,7 +264,7 @@ def test_rbl_plan_validation_and_grid():
     dens = 1000 / 40.0 ** 3
     mc, ms = dens * 4 / 3 * math.pi * 5.0 ** 3, dens * 4 / 3 * math.pi * (10.0 ** 3 - 5.0 ** 3)
     allow = lambda m: m + 6 * math.sqrt(m) + 16
-    assert c[0].value == math.ceil(allow(mc) + min(10, allow(ms))) and c[1].value == 512
+    assert c[0].value == 4 * math.ceil(math.ceil(allow(mc) + min(10, allow(ms))) / 4) and c[1].value == 512
     assert lib.rbl_plan_workspace_bytes(h) >= 1000 * c[0].value * 4
     assert lib.rbl_plan_capacity(None, *[ctypes.byref(a) for a in c]) == _lib.RBE_EINVAL
     assert lib.rbl_plan_set_timing_events(h, None, None, None, None) == 0      # clears, records nothing
