@@ -323,19 +323,22 @@ struct RblArgs {
 // The lanes of the wave whose p is true (a comparison straight into a lane mask).
 __device__ inline uint64_t wave_mask(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
-// The sum of v over the 64 lanes, in every lane's hands.  Data-parallel-primitive moves: an
-// inclusive scan within each row of 16 lanes (shifts right by 1, 2, 4, 8, an empty source
-// giving 0), then row 0's total broadcast into rows 1 and 3 and lane 31's into rows 2 and 3,
-// so lane 63 holds the total.
-__device__ inline int32_t wave_sum(int32_t v) {
+// Inclusive scan of v over the 64 lanes (lane i gets the sum over lanes 0 .. i).
+// Data-parallel-primitive moves: a scan within each row of 16 lanes (shifts right by 1, 2,
+// 4, 8, an empty source giving 0), then lane 15's sum added into rows 1 and 3 and lane 31's
+// into rows 2 and 3 (rows the mask leaves out add 0).
+__device__ inline int32_t wave_scan(int32_t v) {
   v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);   // row_shr:1
   v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);   // row_shr:2
   v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);   // row_shr:4
   v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);   // row_shr:8
   v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
   v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
-  return __builtin_amdgcn_readlane(v, 63);
+  return v;
 }
+
+// The sum of v over the 64 lanes, in every lane's hands.
+__device__ inline int32_t wave_sum(int32_t v) { return __builtin_amdgcn_readlane(wave_scan(v), 63); }
 
 __device__ inline int32_t lanes_below(uint64_t m) {
   return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -373,15 +376,18 @@ __device__ int32_t fill_stencil_window(const RblWs& w, const RblGrid& g, int32_t
       sb = w.range[base + c0].x;
       sl = w.range[base + c1 - 1].y - sb;
     }
-    int32_t incl = sl;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int32_t v = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += v;
-    }
+    const int32_t incl = wave_scan(sl);
     const int32_t ex = T + incl - sl;
     const int32_t lo = max(ex, W0), hi = min(ex + sl, W0 + kListCap);
-    for (int32_t f = lo; f < hi; ++f) list[f - W0] = sb + (f - ex);
-    T += __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
+    // the run's positions: single entries up to a multiple of 4 (W0 is one), then 16 B at a time
+    int32_t f = lo;
+    for (; f < hi && (f & 3) != 0; ++f) list[f - W0] = sb + (f - ex);
+    for (; f + 4 <= hi; f += 4) {
+      const int32_t v = sb + (f - ex);
+      *reinterpret_cast<int4*>(list + (f - W0)) = make_int4(v, v + 1, v + 2, v + 3);
+    }
+    for (; f < hi; ++f) list[f - W0] = sb + (f - ex);
+    T += __builtin_amdgcn_readlane(incl, 63);
   }
   return T;
 }
@@ -413,7 +419,7 @@ __device__ inline double separation(double xi, double yi, double zi, const doubl
 // N_s <= p).  A cell whose stencil exceeds kListCap positions, or a target with more than Q
 // pairs, is left to the fallback.
 __global__ __launch_bounds__(kRblBlock) void rbl_select_kernel(RblWs w, RblArgs a, RblGrid g) {
-  __shared__ int32_t list_[kRblWaves][kListCap];
+  __shared__ __align__(16) int32_t list_[kRblWaves][kListCap];
   __shared__ uint64_t mark_[kRblWaves][kListCap / 8];   // one byte per shell rank
   // blocks are dealt to the XCDs in turn: give each XCD a contiguous run of cells
   const int32_t blk = (int32_t)(blockIdx.x & 7) * a.nblk8 + (int32_t)(blockIdx.x >> 3);
@@ -617,7 +623,7 @@ __global__ __launch_bounds__(kRblBlock) void rbl_pair_kernel(RblWs w, RblArgs a,
 // lane summing its pairs, and a fixed butterfly sums the lanes.
 __global__ __launch_bounds__(kRblBlock) void rbl_fallback_kernel(RblWs w, RblArgs a, RblGrid g, double* __restrict__ F,
                                                                  int32_t* __restrict__ ns_out) {
-  __shared__ int32_t list_[kRblWaves][kListCap];
+  __shared__ __align__(16) int32_t list_[kRblWaves][kListCap];
   __shared__ uint32_t queue_[kRblWaves][64];
   __shared__ int32_t batch_[kRblWaves][kBatchCap];
   const int32_t nfb = __builtin_amdgcn_readfirstlane(*w.nfb);
