@@ -305,7 +305,7 @@ constexpr int kRblWaves = kRblBlock / 64;   // waves per block
 constexpr int kListCap = 512;               // stencil positions held in LDS per wave
 constexpr int kBatchCap = 256;              // batch positions held in LDS per wave (fallback)
 static_assert(kListCap / 64 <= 32, "one bit per chunk in a 32-bit word");
-constexpr int kTgtGroup = 4;                // targets classified together
+constexpr int kTgtGroup = 3;                // targets classified together (2.2 per cell on average)
 constexpr int kFallbackBlocks = 512;
 constexpr int kCorrBlocks = 256;
 constexpr int kMaxPairSlots = 4096;         // pair slots per particle at most
@@ -417,8 +417,10 @@ __device__ inline double separation(double xi, double yi, double zi, const doubl
 // entries -- cell-order index, top bit set for shell members -- into the target's slot of Q
 // entries: every core member, and every shell member whose rank is marked (all of them when
 // N_s <= p).  A cell whose stencil exceeds kListCap positions, or a target with more than Q
-// pairs, is left to the fallback.
-__global__ __launch_bounds__(kRblBlock) void rbl_select_kernel(RblWs w, RblArgs a, RblGrid g) {
+// pairs, is left to the fallback.  The pass waits on LDS and L2 at every chunk, so it keeps
+// 8 waves per SIMD (64 VGPRs with groups of 3 targets).
+__global__ __launch_bounds__(kRblBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void rbl_select_kernel(
+    RblWs w, RblArgs a, RblGrid g) {
   __shared__ __align__(16) int32_t list_[kRblWaves][kListCap];
   __shared__ uint64_t mark_[kRblWaves][kListCap / 8];   // one byte per shell rank
   // blocks are dealt to the XCDs in turn: give each XCD a contiguous run of cells
