@@ -4,8 +4,9 @@
 //
 // One evaluation:
 //   cells   : cell of every particle, per-cell counts (atomic adds), exclusive scan into
-//             cell starts, scatter into cell order (atomic slots), then every cell's short
-//             segment sorted by particle index, so the order is deterministic;
+//             cell starts, scatter into cell order (at the ranks the count atomics gave),
+//             then every cell's short segment sorted by particle index, so the order is
+//             deterministic;
 //   gather  : positions, charges and LJ parameters read in particle order and written into
 //             cell order, and every particle's batch offset u_i drawn;
 //   select  : one wave per cell classifies the cell's stencil against its particles (FP32
@@ -58,7 +59,7 @@ static_assert(sizeof(RblRec) == 64, "RblRec is 64 bytes");
 
 struct RblWs {
   int32_t* count;
-  int32_t* fill;
+  int32_t* rank;     // N, by particle index: its arrival in its cell's count (counting atomics)
   int32_t* start;    // ncell + 1
   int32_t* bsum;     // scan block sums
   int32_t* cell;     // N, by particle index: the cell, then (after the sort) the cell-order position
@@ -97,21 +98,24 @@ __host__ __device__ inline int32_t run_rank(int32_t x, int32_t y, int32_t nc) {
   return (tx << 3) * nc + (ty << 3) * wx + (x & 7) * wy + (y & 7);
 }
 
-__global__ __launch_bounds__(kRblBlock) void rbl_zero_kernel(int32_t* __restrict__ a, int64_t n) {
+// The cell counts and the fallback counter to zero.
+__global__ __launch_bounds__(kRblBlock) void rbl_zero_kernel(int32_t* __restrict__ count, int64_t n,
+                                                             int32_t* __restrict__ nfb) {
   const int64_t i = (int64_t)blockIdx.x * kRblBlock + threadIdx.x;
-  if (i < n) a[i] = 0;
+  if (i < n) count[i] = 0;
+  if (i == 0) *nfb = 0;
 }
 
 __global__ __launch_bounds__(kRblBlock) void rbl_cell_kernel(const double* __restrict__ x,
                                                              const double* __restrict__ y,
                                                              const double* __restrict__ z, int64_t n, double L,
                                                              int32_t nc, int32_t* __restrict__ cell,
-                                                             int32_t* __restrict__ count) {
+                                                             int32_t* __restrict__ count, int32_t* __restrict__ rank) {
   const int64_t i = (int64_t)blockIdx.x * kRblBlock + threadIdx.x;
   if (i >= n) return;
   const int32_t c = run_rank(cell_coord(x[i], L, nc), cell_coord(y[i], L, nc), nc) * nc + cell_coord(z[i], L, nc);
   cell[i] = c;
-  atomicAdd(&count[c], 1);
+  rank[i] = atomicAdd(&count[c], 1);
 }
 
 // Exclusive scan of the cell counts in three launches: per-chunk totals, an in-order scan
@@ -183,13 +187,15 @@ __global__ __launch_bounds__(kRblBlock) void rbl_scan_apply_kernel(const int32_t
   if (blockIdx.x == 0 && threadIdx.x == 0) start[ncell] = (int32_t)n;
 }
 
+// Every particle to its cell's segment, at the place its count atomic gave it (an order the
+// segment sort then makes deterministic).
 __global__ __launch_bounds__(kRblBlock) void rbl_scatter_kernel(const int32_t* __restrict__ cell, int64_t n,
                                                                 const int32_t* __restrict__ start,
-                                                                int32_t* __restrict__ fill, int32_t* __restrict__ idx) {
+                                                                const int32_t* __restrict__ rank,
+                                                                int32_t* __restrict__ idx) {
   const int64_t i = (int64_t)blockIdx.x * kRblBlock + threadIdx.x;
   if (i >= n) return;
-  const int32_t c = cell[i];
-  idx[start[c] + atomicAdd(&fill[c], 1)] = (int32_t)i;
+  idx[start[cell[i]] + rank[i]] = (int32_t)i;
 }
 
 // Each cell's segment in ascending particle index (insertion sort: cells hold a few to a
@@ -814,7 +820,7 @@ void fixed_point_band(double R, double L, float& lo, float& hi) {
 void rbl_layout(rbl_plan* p) {
   const size_t n = (size_t)p->prm.N, nc = (size_t)p->ncell;
   const size_t sizes[17] = {
-      sizeof(int32_t) * nc,        sizeof(int32_t) * nc,           sizeof(int32_t) * (nc + 1),
+      sizeof(int32_t) * nc,        sizeof(int32_t) * n,            sizeof(int32_t) * (nc + 1),
       sizeof(int32_t) * (size_t)(p->nscan + 1), sizeof(int32_t) * n, sizeof(int32_t) * n,
       sizeof(RblRec) * n,          1,                              sizeof(int2) * nc,
       sizeof(double) * n,          sizeof(uint32_t) * 64 * ((n + 63) / 64) * (size_t)p->Q, sizeof(int32_t) * n,
@@ -832,7 +838,7 @@ RblWs rbl_view(const rbl_plan* p, void* ws) {
   char* b = static_cast<char*>(ws);
   RblWs w;
   w.count = reinterpret_cast<int32_t*>(b + p->off[0]);
-  w.fill = reinterpret_cast<int32_t*>(b + p->off[1]);
+  w.rank = reinterpret_cast<int32_t*>(b + p->off[1]);
   w.start = reinterpret_cast<int32_t*>(b + p->off[2]);
   w.bsum = reinterpret_cast<int32_t*>(b + p->off[3]);
   w.cell = reinterpret_cast<int32_t*>(b + p->off[4]);
@@ -935,16 +941,14 @@ rbe_status rbl_short_force(const rbl_plan* p, const double* x, const double* y, 
   const RblGrid& g = p->grid;
   const int64_t nc = p->ncell;
   const rbl_params& prm = p->prm;
-  hipLaunchKernelGGL(rbl_zero_kernel, dim3(blocks_for(nc)), dim3(kRblBlock), 0, s, w.count, nc);
-  hipLaunchKernelGGL(rbl_zero_kernel, dim3(blocks_for(nc)), dim3(kRblBlock), 0, s, w.fill, nc);
-  hipLaunchKernelGGL(rbl_zero_kernel, dim3(1), dim3(kRblBlock), 0, s, w.nfb, (int64_t)1);
+  hipLaunchKernelGGL(rbl_zero_kernel, dim3(blocks_for(nc)), dim3(kRblBlock), 0, s, w.count, nc, w.nfb);
   hipLaunchKernelGGL(rbl_cell_kernel, dim3(blocks_for(n)), dim3(kRblBlock), 0, s, x, y, z, n, prm.L, g.nc, w.cell,
-                     w.count);
+                     w.count, w.rank);
   hipLaunchKernelGGL(rbl_scan_sums_kernel, dim3((unsigned)p->nscan), dim3(kRblBlock), 0, s, w.count, nc, w.bsum);
   hipLaunchKernelGGL(rbl_scan_offsets_kernel, dim3(1), dim3(kRblBlock), 0, s, w.bsum, p->nscan);
   hipLaunchKernelGGL(rbl_scan_apply_kernel, dim3((unsigned)p->nscan), dim3(kRblBlock), 0, s, w.count, nc, w.bsum,
                      w.start, w.range, n);
-  hipLaunchKernelGGL(rbl_scatter_kernel, dim3(blocks_for(n)), dim3(kRblBlock), 0, s, w.cell, n, w.start, w.fill,
+  hipLaunchKernelGGL(rbl_scatter_kernel, dim3(blocks_for(n)), dim3(kRblBlock), 0, s, w.cell, n, w.start, w.rank,
                      w.idx);
   hipLaunchKernelGGL(rbl_segment_sort_kernel, dim3(blocks_for(nc)), dim3(kRblBlock), 0, s, w.start, nc, w.idx, w.cell);
   hipLaunchKernelGGL(rbl_gather_kernel, dim3(blocks_for(n)), dim3(kRblBlock), 0, s, x, y, z, q, eps, sig, n, prm.L,
