@@ -47,13 +47,11 @@ struct RblGrid {
   double inv_nc, inv_nc2;   // 1 / nc, 1 / nc^2
 };
 
-// One particle in cell order: position and charge, sqrt(eps) and sigma, and the position in
-// 32-bit fixed point (frac(x / L) 2^32, so that a wrapping difference is the minimum image)
-// with the particle index.  64 bytes: a pair's data is one cache-line half.
+// One particle in cell order: position and charge, sqrt(eps) and sigma; 48 bytes padded to
+// 64, so that a pair's data is one cache-line half.
 struct alignas(64) RblRec {
   double4 pq;
   double2 lj;
-  uint4 fx;
 };
 static_assert(sizeof(RblRec) == 64, "RblRec is 64 bytes");
 
@@ -65,6 +63,8 @@ struct RblWs {
   int32_t* cell;     // N, by particle index: the cell, then (after the sort) the cell-order position
   int32_t* idx;      // N: particle index at each cell-order position
   RblRec* rec;       // N, in cell order
+  uint4* fxa;        // N, in cell order: the position in 32-bit fixed point, frac(x / L) 2^32 (a
+                     // wrapping difference is the minimum image), read by the selection
   int2* range;       // ncell: first and one-past-last cell-order position of each cell
   double* ru;        // N, in cell order: the particle's batch offset u_i
   uint32_t* slot;    // Q pair entries per particle, interleaved (slot_index)
@@ -239,8 +239,8 @@ __global__ __launch_bounds__(kRblBlock) void rbl_gather_kernel(const double* __r
   RblRec r;
   r.pq = make_double4(x[i], y[i], z[i], q[i]);
   r.lj = make_double2(sqrt(eps[i]), sig[i]);
-  r.fx = make_uint4(fixed_coord(x[i], L), fixed_coord(y[i], L), fixed_coord(z[i], L), (uint32_t)i);
   w.rec[t] = r;
+  w.fxa[t] = make_uint4(fixed_coord(x[i], L), fixed_coord(y[i], L), fixed_coord(z[i], L), 0u);
   U64x4 ctr = {{(uint64_t)i, 0ull, 3ull, 0ull}};
   w.ru[t] = u01_53(philox4x64_10(ctr, seed, step).v[0]);
 }
@@ -466,19 +466,19 @@ __global__ __launch_bounds__(kRblBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
     double ug[kTgtGroup];
 #pragma unroll
     for (int k = 0; k < kTgtGroup; ++k) {
-      tf[k] = w.rec[g0 + min(k, mg - 1)].fx;
+      tf[k] = w.fxa[g0 + min(k, mg - 1)];
       ug[k] = w.ru[g0 + min(k, mg - 1)];
       cb[k] = sb[k] = ab[k] = 0;
     }
     int32_t un = lane < T ? list[lane] : -1;
-    uint4 fn = un >= 0 ? w.rec[un].fx : make_uint4(0u, 0u, 0u, 0u);
+    uint4 fn = un >= 0 ? w.fxa[un] : make_uint4(0u, 0u, 0u, 0u);
     for (int32_t c = 0; c < C; ++c) {
       const int32_t u = un;
       const uint4 fo = fn;
       if (c + 1 < C) {
         const int32_t f = (c + 1) * 64 + lane;
         un = f < T ? list[f] : -1;
-        if (un >= 0) fn = w.rec[un].fx;
+        if (un >= 0) fn = w.fxa[un];
       }
       const uint32_t bit = 1u << c;
 #pragma unroll
@@ -576,7 +576,7 @@ __global__ __launch_bounds__(kRblBlock) void rbl_pair_kernel(RblWs w, RblArgs a,
   if (cnt < 0) return;
   const double4 me = w.rec[t].pq;
   const double2 mlj = w.rec[t].lj;
-  const int32_t i = (int32_t)w.rec[t].fx.w;
+  const int32_t i = w.idx[t];
   const int32_t ns = w.tns[t];
   const double wgt = ns > a.p ? (double)ns / (double)a.p : 1.0;
   // this particle's groups of 4 entries, 64 groups (1 KB) apart
@@ -822,7 +822,7 @@ void rbl_layout(rbl_plan* p) {
   const size_t sizes[17] = {
       sizeof(int32_t) * nc,        sizeof(int32_t) * n,            sizeof(int32_t) * (nc + 1),
       sizeof(int32_t) * (size_t)(p->nscan + 1), sizeof(int32_t) * n, sizeof(int32_t) * n,
-      sizeof(RblRec) * n,          1,                              sizeof(int2) * nc,
+      sizeof(RblRec) * n,          sizeof(uint4) * n,              sizeof(int2) * nc,
       sizeof(double) * n,          sizeof(uint32_t) * 64 * ((n + 63) / 64) * (size_t)p->Q, sizeof(int32_t) * n,
       sizeof(int32_t) * n,         sizeof(int32_t) * n,            sizeof(int32_t),
       sizeof(double) * 3 * kCorrBlocks, sizeof(double) * 3};
@@ -844,6 +844,7 @@ RblWs rbl_view(const rbl_plan* p, void* ws) {
   w.cell = reinterpret_cast<int32_t*>(b + p->off[4]);
   w.idx = reinterpret_cast<int32_t*>(b + p->off[5]);
   w.rec = reinterpret_cast<RblRec*>(b + p->off[6]);
+  w.fxa = reinterpret_cast<uint4*>(b + p->off[7]);
   w.range = reinterpret_cast<int2*>(b + p->off[8]);
   w.ru = reinterpret_cast<double*>(b + p->off[9]);
   w.slot = reinterpret_cast<uint32_t*>(b + p->off[10]);
