@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: 5 eager evaluations per form plus a 256 MiB device copy "
                          "(the reference kernel of known size for HBM counter scaling); prints no JSON")
+    ap.add_argument("--profile-rbl", action="store_true",
+                    help="short run for rocprofv3: 5 RBL evaluations of the 1M electrolyte at p = 30, then 5 "
+                         "at p = 100; prints no JSON")
     return ap.parse_args()
 
 
@@ -138,6 +141,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.profile_rbl:
+        profile_rbl(torch, ri, dev)
+        return
     t_gen = time.perf_counter()
     s, alpha, P = ri.c3a_electrolyte()
     log(f"generated {s.name} (N={s.n}, L={s.L:.4f}) in {time.perf_counter() - t_gen:.1f}s")
@@ -254,6 +260,19 @@ def profile_run(torch, Plan, Batch, X, s, alpha, P, dev):
         dst.copy_(src)
     torch.cuda.synchronize()
     log("profile copy: 3 x 256 MiB")
+
+
+def profile_rbl(torch, ri, dev):
+    from paper_2407_09315_amd import RBLPlan
+    s = ri.primitive_electrolyte(1_000_000, 0.01, 1006)
+    X = [torch.tensor(a, dtype=torch.float64, device=dev) for a in (s.x, s.y, s.z, s.q, s.eps, s.sig)]
+    for p in (30, 100):
+        plan = RBLPlan(s.n, s.L, 0.06, 6.0, 12.0, p, device=dev)
+        F, ns = plan.short_force(*X, seed=1, step=0)
+        for k in range(1, 5):
+            plan.short_force(*X, seed=1, step=k, F=F, ns=ns)
+        torch.cuda.synchronize()
+        log(f"profile rbl p={p}: 5 evaluations")
 
 
 def rho_kernel_name(plan):
