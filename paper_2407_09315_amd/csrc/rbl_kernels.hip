@@ -541,14 +541,20 @@ __global__ __launch_bounds__(kRblBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
         for (int32_t b = lane; b < a.p; b += 64) mark[batch_pos(b, uoff, ns, a.p)] = 1;
         wave_sync();
       }
+      // entry j of the target sits at out[(j / 4) 256 + j mod 4] (slot_index)
+      uint32_t* const out = w.slot + slot_index(t, a.Q, 0);
+      const uint32_t ubits = cbits | sbits;
       int32_t pos0 = 0, rank0 = 0;
       for (int32_t c = 0; c < C; ++c) {
         const bool shell = (sbits >> c) & 1;
         const uint64_t sm = wave_mask(shell);
-        bool use = (cbits >> c) & 1;
-        if (shell) use = !sub || mark[rank0 + lanes_below(sm)] != 0;
+        bool use = (ubits >> c) & 1;
+        if (sub && shell) use = mark[rank0 + lanes_below(sm)] != 0;
         const uint64_t U = wave_mask(use);
-        if (use) w.slot[slot_index(t, a.Q, pos0 + lanes_below(U))] = (uint32_t)list[c * 64 + lane] | (shell ? 0x80000000u : 0u);
+        if (use) {
+          const uint32_t j = (uint32_t)(pos0 + lanes_below(U));
+          out[((j >> 2) << 8) | (j & 3u)] = (uint32_t)list[c * 64 + lane] | (shell ? 0x80000000u : 0u);
+        }
         pos0 += __popcll(U);
         rank0 += __popcll(sm);
       }
