@@ -5,8 +5,8 @@
     particle count off the block size, a box whose stencil wraps, a batch larger than
     every shell (the exact truncated force), a dense box whose cells hold more than one
     group of targets and whose stencil is streamed in windows, r_c = r_s (no shell), 50
-    particles with p = 1, and a packed cluster whose particles have more pairs than the fast
-    path's slots;
+    particles with p = 1, a packed cluster whose particles have more pairs than the fast
+    path's slots, and systems of 1, 2 and 7 particles (one in a box of mostly empty cells);
   * the 1M-particle benchmark system: N_s exact and the raw force differences F_i - F_0 of
     sampled particles (the momentum correction is one vector for all) against the oracle's
     brute-force raw forces of those particles, and sum_i F_i = 0;
@@ -66,6 +66,36 @@ def test_rbl_parity(n, density, alpha, rc, rs, p, unequal):
     note(f"  force rel RMS {ef:.2e}, max {em:.2e}, mean N_s {ns.mean():.1f}")
     assert ef < 1e-12 and em < 1e-11
     assert np.all(np.abs(F.sum(axis=1)) < 1e-11 * np.abs(F).sum(axis=1))
+    plan.close()
+
+
+@pytest.mark.parametrize("n,L,spread", [(1, 30.0, None), (2, 30.0, 2.5), (7, 30.0, None), (7, 60.0, 5.0),
+                                         (7, 60.0, None)])
+def test_rbl_parity_tiny(n, L, spread):
+    """A handful of particles with random charges: one particle alone (no pairs, zero force),
+    a close pair, 7 scattered particles, and 7 particles in a box of 1,728 cells, almost all
+    of them empty, either clustered (core and shell pairs) or scattered (no pairs at all)."""
+    g = np.random.default_rng(900 + n)
+    if spread is None:
+        x, y, z = (g.uniform(0.0, L, n) for _ in range(3))
+    else:
+        x, y, z = (g.uniform(0.0, L) + g.uniform(-spread, spread, n) for _ in range(3))
+    q = g.choice([-1.0, 1.0], n)
+    eps, sig = g.uniform(0.5, 1.5, n), g.uniform(0.8, 1.3, n)
+    alpha, rc, rs, p, seed, step = 0.1, 5.0, 10.0, 3, 5, 2
+    note(f"case rbl tiny n={n} L={L} spread={spread}")
+    plan = RBLPlan(n, L, alpha, rc, rs, p, device=dev())
+    X = [to_dev(a) for a in (x, y, z, q, eps, sig)]
+    F, ns = plan.short_force(*X, seed=seed, step=step)
+    torch.cuda.synchronize()
+    F, ns = F.cpu().numpy(), ns.cpu().numpy()
+    F_ref, ns_ref = oracle.rbl_short_force(x, y, z, q, eps, sig, L, alpha, rc, rs, p, oracle.rbl_offsets(seed, step, n))
+    note(f"  grid {plan.grid()}, N_s {ns.tolist()}")
+    assert np.array_equal(ns, ns_ref)
+    if not np.any(F_ref != 0.0):
+        assert np.all(F == 0.0)
+    else:
+        assert force_err(F, F_ref) < 1e-12 and max_err(F, F_ref) < 1e-11
     plan.close()
 
 
