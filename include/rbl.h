@@ -38,8 +38,9 @@
  * Work split: the fast path holds a cell's stencil of up to `stencil_positions` particles
  * in on-chip memory and up to `pairs_per_particle` core and batch pairs per particle in the
  * workspace (rbl_plan_capacity; sized from the mean density N / L^3 with a wide Poisson
- * allowance, at most 4096).  Particles beyond either take a slower path with the same result; the sum
- * order of a particle's pairs differs between the two, by rounding only.
+ * allowance, a multiple of 4, at most 4096).  Particles beyond either take a slower path
+ * with the same result; the sum order of a particle's pairs differs between the two, by
+ * rounding only.
  */
 #ifndef RBL_H
 #define RBL_H
