@@ -74,6 +74,7 @@ struct RblWs {
   int32_t* nfb;      // 1: their count
   double* partial;   // 3 per block of the first summation
   double* corr;      // 3
+  double* etab;      // erfcx table: kErfcCoef Taylor coefficients per interval (erfcx_table)
 };
 
 // Cell coordinate of a position along one axis: min(floor(frac(x / L) nc), nc - 1).  A
@@ -87,6 +88,48 @@ __device__ inline int32_t cell_coord(double x, double L, int32_t nc) {
   return c < nc - 1 ? c : nc - 1;
 }
 
+// erfc(x) = exp(-x^2) erfcx(x), with erfcx tabulated on [0, x_tab] as degree-9 Taylor
+// polynomials around the centres of intervals of width x_tab / eni <= 0.1
+constexpr int kErfcDeg = 9;
+constexpr int kErfcCoef = kErfcDeg + 1;
+constexpr int kErfcMaxIntervals = 256;
+constexpr double kErfcMaxX = 25.6;          // erfc(25.6) = 2e-287: zero beyond, to the force
+
+// Interval k of the erfcx table: erfcx(x_k + t h / 2) = sum_j c_j t^j, t in [-1, 1], around the
+// centre x_k = (k + 1/2) h, with c_j = erfcx^(j)(x_k) (h / 2)^j / j!.  The derivatives follow
+// from erfcx' = 2 x erfcx - 2 / sqrt(pi), differentiated n times:
+// erfcx^(n+1) = 2 x erfcx^(n) + 2 n erfcx^(n-1).  (Each error in erfcx(x_k) grows along the
+// recurrence as (2 x_k)^n, which the factor (h / 2)^n / n! more than cancels for h <= 0.1.)
+__device__ inline void erfcx_interval(double* __restrict__ c, int32_t k, double h) {
+  const double xc = ((double)k + 0.5) * h, hw = 0.5 * h;
+  double d0 = erfc(xc) * exp(xc * xc);
+  double d1 = 2.0 * xc * d0 - 1.1283791670955125739;   // 2 / sqrt(pi)
+  c[0] = d0;
+  double f = hw;
+  c[1] = d1 * f;
+  for (int j = 1; j < kErfcDeg; ++j) {
+    const double d2 = 2.0 * xc * d1 + 2.0 * (double)j * d0;
+    f *= hw / (double)(j + 1);
+    c[j + 1] = d2 * f;
+    d0 = d1;
+    d1 = d2;
+  }
+}
+
+// erfcx(x) for 0 <= x from the table: the last interval also takes x a rounding past its end,
+// and x >= kErfcMaxX gives 0 (exp(-x^2) erfcx(x) < 1e-286 there).  A NaN x gives NaN.
+__device__ inline double erfcx_table(const double* __restrict__ tab, int32_t ni, double inv, double x) {
+  if (x >= kErfcMaxX) return 0.0;
+  const double u = x * inv;
+  const int32_t k = min(max((int32_t)u, 0), ni - 1);
+  const double t = 2.0 * (u - (double)k) - 1.0;
+  const double* c = tab + k * kErfcCoef;
+  double p = c[kErfcDeg];
+#pragma unroll
+  for (int j = kErfcDeg - 1; j >= 0; --j) p = fma(p, t, c[j]);
+  return p;
+}
+
 // Memory order of the cells: z runs are contiguous, and the nc^2 runs are laid out in tiles of
 // 8 x 8 (x, y) runs, x-major over the tiles and within a tile, so that a contiguous range of
 // cells (and of particles in cell order) is compact in space.  The rank of run (x, y):
@@ -98,12 +141,15 @@ __host__ __device__ inline int32_t run_rank(int32_t x, int32_t y, int32_t nc) {
   return (tx << 3) * nc + (ty << 3) * wx + (x & 7) * wy + (y & 7);
 }
 
-// The cell counts and the fallback counter to zero.
+// The cell counts and the fallback counter to zero; the first eni threads also write the
+// erfcx table (erfcx_interval, intervals of width h).
 __global__ __launch_bounds__(kRblBlock) void rbl_zero_kernel(int32_t* __restrict__ count, int64_t n,
-                                                             int32_t* __restrict__ nfb) {
+                                                             int32_t* __restrict__ nfb, double* __restrict__ etab,
+                                                             int32_t eni, double h) {
   const int64_t i = (int64_t)blockIdx.x * kRblBlock + threadIdx.x;
   if (i < n) count[i] = 0;
   if (i == 0) *nfb = 0;
+  if (i < eni) erfcx_interval(etab + i * kErfcCoef, (int32_t)i, h);
 }
 
 __global__ __launch_bounds__(kRblBlock) void rbl_cell_kernel(const double* __restrict__ x,
@@ -264,8 +310,11 @@ __device__ inline double dist2(double dx, double dy, double dz) {
 
 // Force on i from j given d = r_i - r_j and r2 = |d|^2, added into f (Eqs. lj and fshort),
 // with the mixed LJ well depth as sqrt(eps_i) sqrt(eps_j) and one division, 1 / r^2.
+// The pair force of Eq. (lj) and (fshort) on i from j, added to (fx, fy, fz); erfc(sqrt(alpha) r)
+// as exp(-alpha r^2) erfcx(sqrt(alpha) r), the exponential shared with the Gaussian term.
 __device__ inline void pair_force_add(double qi, double qj, double rei, double rej, double si, double sj,
-                                      double alpha, double sqa, double tsap, double dx, double dy, double dz,
+                                      double alpha, double sqa, double tsap, const double* __restrict__ etab,
+                                      int32_t eni, double einv, double dx, double dy, double dz,
                                       double r2, double& fx, double& fy, double& fz) {
   const double ir2 = 1.0 / r2;
   const double r = sqrt(r2);
@@ -279,7 +328,8 @@ __device__ inline void pair_force_add(double qi, double qj, double rei, double r
     g += 24.0 * e * (2.0 * s6 * s6 - s6) * ir2;
   }
   if (qi != 0.0 && qj != 0.0) {
-    const double kern = erfc(sqa * r) * ir2 + tsap * exp(-alpha * r2) * ir;
+    const double ex = exp(-alpha * r2);
+    const double kern = ex * (erfcx_table(etab, eni, einv, sqa * r) * ir2 + tsap * ir);
     g += qi * qj * kern * ir;
   }
   fx += g * dx;
@@ -320,6 +370,8 @@ struct RblArgs {
   int64_t n, ncell;
   int32_t nblk, nblk8;   // blocks of the select kernel and that count over the 8 XCDs, rounded up
   int32_t p, Q;          // batch size, pair slots per particle
+  int32_t eni;           // intervals of the erfcx table
+  double einv;           // intervals per unit of x = sqrt(alpha) r
   double L, invL, alpha, sqa, tsap, rc2, rs2;
   // r_c^2 and r_s^2 in fixed-point units^2, each widened to a band [lo, hi] that holds every
   // squared distance the fixed-point FP32 estimate cannot place on one side
@@ -574,6 +626,9 @@ __global__ __launch_bounds__(kRblBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
 // pairs times N_s / p.
 __global__ __launch_bounds__(kRblBlock) void rbl_pair_kernel(RblWs w, RblArgs a, double* __restrict__ F,
                                                              int32_t* __restrict__ ns_out) {
+  __shared__ double etab[kErfcMaxIntervals * kErfcCoef];   // the erfcx table
+  for (int i = threadIdx.x; i < a.eni * kErfcCoef; i += kRblBlock) etab[i] = w.etab[i];
+  __syncthreads();
   const int32_t nb = (int32_t)((a.n + kRblBlock - 1) / kRblBlock), nb8 = (nb + 7) / 8;
   const int32_t blk = (int32_t)(blockIdx.x & 7) * nb8 + (int32_t)(blockIdx.x >> 3);
   const int64_t t = (int64_t)blk * kRblBlock + threadIdx.x;
@@ -617,7 +672,8 @@ __global__ __launch_bounds__(kRblBlock) void rbl_pair_kernel(RblWs w, RblArgs a,
     double dx, dy, dz;
     const double r2 = separation(me.x, me.y, me.z, o, a.L, a.invL, dx, dy, dz);
     double px = 0.0, py = 0.0, pz = 0.0;
-    pair_force_add(me.w, o.w, mlj.x, olj.x, mlj.y, olj.y, a.alpha, a.sqa, a.tsap, dx, dy, dz, r2, px, py, pz);
+    pair_force_add(me.w, o.w, mlj.x, olj.x, mlj.y, olj.y, a.alpha, a.sqa, a.tsap, etab, a.eni, a.einv, dx, dy, dz, r2,
+                   px, py, pz);
     const double wt = (ej >> 31) ? wgt : 1.0;
     ax += wt * px;
     ay += wt * py;
@@ -701,7 +757,8 @@ __global__ __launch_bounds__(kRblBlock) void rbl_fallback_kernel(RblWs w, RblArg
         double dx, dy, dz;
         const double r2 = separation(me.x, me.y, me.z, o, a.L, a.invL, dx, dy, dz);
         double px = 0.0, py = 0.0, pz = 0.0;
-        pair_force_add(me.w, o.w, mlj.x, olj.x, mlj.y, olj.y, a.alpha, a.sqa, a.tsap, dx, dy, dz, r2, px, py, pz);
+        pair_force_add(me.w, o.w, mlj.x, olj.x, mlj.y, olj.y, a.alpha, a.sqa, a.tsap, w.etab, a.eni, a.einv, dx, dy,
+                       dz, r2, px, py, pz);
         const double wt = (e >> 31) ? wgt : 1.0;
         ax += wt * px;
         ay += wt * py;
@@ -791,7 +848,9 @@ struct rbl_plan {
   int32_t nscan = 0;     // scan blocks
   int32_t nsel = 0;      // select blocks (kRblWaves cells each)
   int32_t Q = 0;         // pair slots per particle
-  size_t off[17] = {};
+  int32_t eni = 1;       // erfcx table: intervals and their width in x = sqrt(alpha) r
+  double eh = 0.1;
+  size_t off[18] = {};
   size_t bytes = 0;
   hipEvent_t ev[4] = {};  // caller's events around the select and pair kernels (optional)
 };
@@ -825,15 +884,15 @@ void fixed_point_band(double R, double L, float& lo, float& hi) {
 
 void rbl_layout(rbl_plan* p) {
   const size_t n = (size_t)p->prm.N, nc = (size_t)p->ncell;
-  const size_t sizes[17] = {
+  const size_t sizes[18] = {
       sizeof(int32_t) * nc,        sizeof(int32_t) * n,            sizeof(int32_t) * (nc + 1),
       sizeof(int32_t) * (size_t)(p->nscan + 1), sizeof(int32_t) * n, sizeof(int32_t) * n,
       sizeof(RblRec) * n,          sizeof(uint4) * n,              sizeof(int2) * nc,
       sizeof(double) * n,          sizeof(uint32_t) * 64 * ((n + 63) / 64) * (size_t)p->Q, sizeof(int32_t) * n,
       sizeof(int32_t) * n,         sizeof(int32_t) * n,            sizeof(int32_t),
-      sizeof(double) * 3 * kCorrBlocks, sizeof(double) * 3};
+      sizeof(double) * 3 * kCorrBlocks, sizeof(double) * 3, sizeof(double) * kErfcMaxIntervals * kErfcCoef};
   size_t o = 0;
-  for (int k = 0; k < 17; ++k) {
+  for (int k = 0; k < 18; ++k) {
     p->off[k] = o;
     o = rbl_align(o + std::max<size_t>(sizes[k], 1));
   }
@@ -860,6 +919,7 @@ RblWs rbl_view(const rbl_plan* p, void* ws) {
   w.nfb = reinterpret_cast<int32_t*>(b + p->off[14]);
   w.partial = reinterpret_cast<double*>(b + p->off[15]);
   w.corr = reinterpret_cast<double*>(b + p->off[16]);
+  w.etab = reinterpret_cast<double*>(b + p->off[17]);
   return w;
 }
 
@@ -898,6 +958,13 @@ rbe_status rbl_plan_create(const rbl_params* prm, rbl_plan** out) {
   p->nscan = (int32_t)((p->ncell + kScanChunk - 1) / kScanChunk);
   p->nsel = (int32_t)((p->ncell + kRblWaves - 1) / kRblWaves);
   p->Q = pair_slots(q);
+  {
+    // the table covers x up to sqrt(alpha) r_s (at least 0.1, at most kErfcMaxX) in intervals
+    // of width at most 0.1
+    const double x_tab = std::min(std::max(std::sqrt(q.alpha) * q.r_s, 0.1), kErfcMaxX);
+    p->eni = std::min(std::max((int32_t)std::ceil(x_tab / 0.1), 1), kErfcMaxIntervals);
+    p->eh = x_tab / (double)p->eni;
+  }
   rbl_layout(p);
   *out = p;
   return RBE_OK;
@@ -948,7 +1015,8 @@ rbe_status rbl_short_force(const rbl_plan* p, const double* x, const double* y, 
   const RblGrid& g = p->grid;
   const int64_t nc = p->ncell;
   const rbl_params& prm = p->prm;
-  hipLaunchKernelGGL(rbl_zero_kernel, dim3(blocks_for(nc)), dim3(kRblBlock), 0, s, w.count, nc, w.nfb);
+  hipLaunchKernelGGL(rbl_zero_kernel, dim3(blocks_for(std::max<int64_t>(nc, kErfcMaxIntervals))), dim3(kRblBlock), 0,
+                     s, w.count, nc, w.nfb, w.etab, p->eni, p->eh);
   hipLaunchKernelGGL(rbl_cell_kernel, dim3(blocks_for(n)), dim3(kRblBlock), 0, s, x, y, z, n, prm.L, g.nc, w.cell,
                      w.count, w.rank);
   hipLaunchKernelGGL(rbl_scan_sums_kernel, dim3((unsigned)p->nscan), dim3(kRblBlock), 0, s, w.count, nc, w.bsum);
@@ -967,6 +1035,8 @@ rbe_status rbl_short_force(const rbl_plan* p, const double* x, const double* y, 
   a.nblk8 = (p->nsel + 7) / 8;
   a.p = prm.p;
   a.Q = p->Q;
+  a.eni = p->eni;
+  a.einv = 1.0 / p->eh;
   a.L = prm.L;
   a.invL = 1.0 / prm.L;
   a.alpha = prm.alpha;
