@@ -3,9 +3,9 @@
   * whole systems (every force, every N_s) on the same batch offsets: the primitive
     electrolyte at the paper's density with p = 30 and 100, unequal LJ parameters, a
     particle count off the block size, a box whose stencil wraps, a batch larger than
-    every shell (the exact truncated force), a dense box whose cells hold more than one
-    group of targets and whose stencil is streamed in windows, r_c = r_s (no shell), 50
-    particles with p = 1, a packed cluster whose particles have more pairs than the fast
+    every shell (the exact truncated force), alpha = 0 and sqrt(alpha) r_s = 17 (the ends of
+    the erfcx table), a dense box whose cells hold more than one group of targets and whose
+    stencil is streamed in windows, r_c = r_s (no shell), 50 particles with p = 1, a packed cluster whose particles have more pairs than the fast
     path's slots, and systems of 1, 2 and 7 particles (one in a box of mostly empty cells);
   * the 1M-particle benchmark system: N_s exact and the raw force differences F_i - F_0 of
     sampled particles (the momentum correction is one vector for all) against the oracle's
@@ -45,6 +45,8 @@ CASES = [
     (2000, 1.0, 0.3, 2.5, 5.0, 20, True),        # 16 per cell, stencils of 2000 positions
     (2000, 0.01, 0.06, 8.0, 8.0, 30, False),     # r_c = r_s: the two bands coincide, no shell
     (50, 0.01, 0.1, 3.0, 8.0, 1, True),          # 50 particles, p = 1, the stencil wraps
+    (2000, 0.01, 0.0, 6.0, 12.0, 30, True),      # alpha = 0: erfc = 1, the erfcx table is one interval
+    (2000, 0.01, 2.0, 6.0, 12.0, 30, True),      # sqrt(alpha) r_s = 17: 170 table intervals
 ]
 
 
