@@ -98,8 +98,9 @@ constexpr double kErfcMaxX = 25.6;          // erfc(25.6) = 2e-287: zero beyond,
 // Interval k of the erfcx table: erfcx(x_k + t h / 2) = sum_j c_j t^j, t in [-1, 1], around the
 // centre x_k = (k + 1/2) h, with c_j = erfcx^(j)(x_k) (h / 2)^j / j!.  The derivatives follow
 // from erfcx' = 2 x erfcx - 2 / sqrt(pi), differentiated n times:
-// erfcx^(n+1) = 2 x erfcx^(n) + 2 n erfcx^(n-1).  (Each error in erfcx(x_k) grows along the
-// recurrence as (2 x_k)^n, which the factor (h / 2)^n / n! more than cancels for h <= 0.1.)
+// erfcx^(n+1) = 2 x erfcx^(n) + 2 n erfcx^(n-1).  (An error in erfcx(x_k) grows along the
+// recurrence as (2 x_k)^n and reaches c_n times (x_k h)^n / n!: at most e^(x_k h) < 13 in all
+// for x_k <= 25.6 and h <= 0.1, and near 1 for the x_k h < 0.3 of typical cutoffs.)
 __device__ inline void erfcx_interval(double* __restrict__ c, int32_t k, double h) {
   const double xc = ((double)k + 0.5) * h, hw = 0.5 * h;
   double d0 = erfc(xc) * exp(xc * xc);
