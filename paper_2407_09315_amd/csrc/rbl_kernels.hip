@@ -472,10 +472,11 @@ __device__ inline double separation(double xi, double yi, double zi, const doubl
 // differences in FP32; each lane keeps one core bit and one shell bit per chunk and target;
 // where the estimate falls in a band around r_c^2 or r_s^2 the lane is classified afterwards
 // with the FP64 distance of the definition.  The batch draws mark their shell ranks
-// floor((b + u) N_s / p) in an LDS byte array, and one sweep over the chunks writes the pair
-// entries -- cell-order index, top bit set for shell members -- into the target's slot of Q
-// entries: every core member, and every shell member whose rank is marked (all of them when
-// N_s <= p).  A cell whose stencil exceeds kListCap positions, or a target with more than Q
+// floor((b + u) N_s / p) in an LDS byte array, and each lane writes the pair entries it holds
+// -- cell-order index, top bit set for shell members -- into the target's slot of Q entries
+// from a wave prefix sum of the lanes' counts: every core member, and every shell member
+// whose rank is marked (all of them when N_s <= p).  A cell whose stencil exceeds kListCap
+// positions, or a target with more than Q
 // pairs, is left to the fallback.  The pass waits on LDS and L2 at every chunk, so it keeps
 // 8 waves per SIMD (64 VGPRs with groups of 3 targets).
 __global__ __launch_bounds__(kRblBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void rbl_select_kernel(
@@ -594,22 +595,34 @@ __global__ __launch_bounds__(kRblBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
         for (int32_t b = lane; b < a.p; b += 64) mark[batch_pos(b, uoff, ns, a.p)] = 1;
         wave_sync();
       }
-      // entry j of the target sits at out[(j / 4) 256 + j mod 4] (slot_index)
-      uint32_t* const out = w.slot + slot_index(t, a.Q, 0);
-      const uint32_t ubits = cbits | sbits;
-      int32_t pos0 = 0, rank0 = 0;
-      for (int32_t c = 0; c < C; ++c) {
-        const bool shell = (sbits >> c) & 1;
-        const uint64_t sm = wave_mask(shell);
-        bool use = (ubits >> c) & 1;
-        if (sub && shell) use = mark[rank0 + lanes_below(sm)] != 0;
-        const uint64_t U = wave_mask(use);
-        if (use) {
-          const uint32_t j = (uint32_t)(pos0 + lanes_below(U));
-          out[((j >> 2) << 8) | (j & 3u)] = (uint32_t)list[c * 64 + lane] | (shell ? 0x80000000u : 0u);
+      // the lane's candidates the target uses: every core member, and every shell member
+      // whose rank (in traversal order: chunks, then lanes) is marked -- all of them when
+      // N_s <= p
+      uint32_t ubits = cbits;
+      if (sub) {
+        int32_t rank0 = 0;
+        for (int32_t c = 0; c < C; ++c) {
+          const bool shell = (sbits >> c) & 1;
+          const uint64_t sm = wave_mask(shell);
+          if (shell && mark[rank0 + lanes_below(sm)] != 0) ubits |= 1u << c;
+          rank0 += __popcll(sm);
         }
-        pos0 += __popcll(U);
-        rank0 += __popcll(sm);
+      } else {
+        ubits |= sbits;
+      }
+      // every lane writes its entries in chunk order from its prefix offset (the slot holds
+      // them by lane, then by chunk); entry j of the target sits at out[(j / 4) 256 + j mod 4]
+      // (slot_index)
+      uint32_t* const out = w.slot + slot_index(t, a.Q, 0);
+      const int32_t mine = __popc(ubits);
+      const int32_t incl = wave_scan(mine);
+      const int32_t pos0 = __builtin_amdgcn_readlane(incl, 63);
+      uint32_t j = (uint32_t)(incl - mine);
+      while (ubits != 0) {
+        const int32_t c = __builtin_ctz(ubits);
+        ubits &= ubits - 1;
+        out[((j >> 2) << 8) | (j & 3u)] = (uint32_t)list[c * 64 + lane] | (((sbits >> c) & 1) ? 0x80000000u : 0u);
+        ++j;
       }
       if (sub) {
         wave_sync();
