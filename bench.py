@@ -60,7 +60,7 @@ def parse():
                          "(the reference kernel of known size for HBM counter scaling); prints no JSON")
     ap.add_argument("--profile-rbl", action="store_true",
                     help="short run for rocprofv3: 5 RBL evaluations of the 1M electrolyte at p = 30, then 5 "
-                         "at p = 100; prints no JSON")
+                         "at p = 100, then a 256 MiB device copy (for HBM counter scaling); prints no JSON")
     return ap.parse_args()
 
 
@@ -273,6 +273,12 @@ def profile_rbl(torch, ri, dev):
             plan.short_force(*X, seed=1, step=k, F=F, ns=ns)
         torch.cuda.synchronize()
         log(f"profile rbl p={p}: 5 evaluations")
+    src = torch.ones(256 * 2 ** 20 // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("profile copy: 3 x 256 MiB")
 
 
 def rho_kernel_name(plan):
@@ -303,6 +309,28 @@ def traffic_from_profile(kernel: str):
         return float(fields["hbm bytes per launch"])
     except (KeyError, ValueError):
         return None
+
+
+def rbl_traffic_from_profile(kernel: str, p: int):
+    """HBM bytes per launch of the RBL `kernel` at batch size p (30 or 100) from the committed
+    counter summary, or None when it is missing or was taken on a different kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "counters_rbl_electrolyte_1M.md")
+    src = os.path.join(ROOT, "paper_2407_09315_amd", "csrc", "rbl_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    text = open(path).read()
+    if f"kernel source sha256 (rbl_kernels.hip): {digest}" not in text:
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 7 and cells[0] == f"`{kernel}`" and cells[1] == str(p):
+            try:
+                return float(cells[4].replace(",", "")) * 1e6
+            except ValueError:
+                return None
+    return None
 
 
 def cpu_info():
@@ -473,8 +501,8 @@ def bench_rbl(torch, ri, dev, steps, with_cpu=True):
                                 "Lennard-Jones with the mixing rules 13, real-space Coulomb 12, "
                                 f"sum 6; erfc, exp, sqrt, divide as one each); {pairs / s.n:.2f} pairs per particle")}
         roof = {k: {"bound": "alu", "kernel": k, "achieved": round(f / t / 1e12, 3), "peak": 78.6,
-                    "unit": "TFLOP/s", "frac": round(f / t / 78.6e12, 4), "traffic": None, "work": w,
-                    "kernel_ms": round(t * 1e3, 4)}
+                    "unit": "TFLOP/s", "frac": round(f / t / 78.6e12, 4),
+                    "traffic": rbl_traffic_from_profile(k, p), "work": w, "kernel_ms": round(t * 1e3, 4)}
                 for k, (t, f, w) in lines.items()}
         dom = max(roof, key=lambda k: roof[k]["kernel_ms"])
         key = f"rbl_short_force_electrolyte_1M_p{p}"
