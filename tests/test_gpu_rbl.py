@@ -5,7 +5,8 @@
     particle count off the block size, a box whose stencil wraps, a batch larger than
     every shell (the exact truncated force), alpha = 0 and sqrt(alpha) r_s = 17 (the ends of
     the erfcx table), a dense box whose cells hold more than one group of targets and whose
-    stencil is streamed in windows, r_c = r_s (no shell), 50 particles with p = 1, a packed cluster whose particles have more pairs than the fast
+    stencil is streamed in windows, r_c = r_s (no shell), 50 particles with p = 1, pairs at
+    r_c and r_s to within 1e-10 (the FP64 decisions inside the selection's bands), a packed cluster whose particles have more pairs than the fast
     path's slots, and systems of 1, 2 and 7 particles (one in a box of mostly empty cells);
   * the 1M-particle benchmark system: N_s exact and the raw force differences F_i - F_0 of
     sampled particles (the momentum correction is one vector for all) against the oracle's
@@ -98,6 +99,65 @@ def test_rbl_parity_tiny(n, L, spread):
         assert np.all(F == 0.0)
     else:
         assert force_err(F, F_ref) < 1e-12 and max_err(F, F_ref) < 1e-11
+    plan.close()
+
+
+def _cutoff_band_system():
+    """The electrolyte of 2,000 particles with 8 centres (L/2 apart, so that their groups do not
+    meet), each with 5 particles at r_c (1 + d) and 5 at r_s (1 + d), d in {-1e-10, -1e-14, 0,
+    1e-14, 1e-10}, along the directions of an icosahedron's vertices: squared distances
+    inside the bands of the fixed-point estimate, which the FP64 distance decides.  The
+    grid is offset by L/8 so that half of the groups straddle the periodic boundary.
+    Background particles within 1.5 of any placed one are dropped."""
+    s = ri.primitive_electrolyte(2000, 0.01, 777)
+    rc, rs, L = 6.0, 12.0, s.L
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    ico = np.array([(0, 1, t), (0, -1, t), (0, 1, -t), (0, -1, -t), (1, t, 0), (-1, t, 0), (1, -t, 0), (-1, -t, 0),
+                    (t, 0, 1), (t, 0, -1)], float)
+    ico /= np.linalg.norm(ico, axis=1, keepdims=True)
+    deltas = [-1e-10, -1e-14, 0.0, 1e-14, 1e-10]
+    placed = []
+    for cx in (0, 1):
+        for cy in (0, 1):
+            for cz in (0, 1):
+                c = np.array([cx, cy, cz]) * (L / 2) + L / 8 + (L / 2 - L / 8) * (cx == 0)
+                c = np.mod(c - (L / 4 if cx == cy else 0.0), L)
+                placed.append(c)
+                for k, d in enumerate(deltas):
+                    placed.append(c + rc * (1.0 + d) * ico[k])
+                    placed.append(c + rs * (1.0 + d) * ico[5 + k])
+    placed = np.array(placed)
+    base = np.stack([s.x, s.y, s.z], 1)
+    diff = base[:, None, :] - placed[None, :, :]
+    diff -= L * np.rint(diff / L)
+    keep = np.min(np.linalg.norm(diff, axis=2), axis=1) > 1.5
+    pos = np.concatenate([placed, base[keep]])
+    g = np.random.default_rng(5)
+    q = np.concatenate([g.choice([-1.0, 1.0], len(placed)), s.q[keep]])
+    eps = np.concatenate([g.uniform(0.5, 1.5, len(placed)), s.eps[keep]])
+    sig = np.concatenate([g.uniform(0.8, 1.3, len(placed)), s.sig[keep]])
+    return pos, q, eps, sig, L, len(placed)
+
+
+@pytest.mark.parametrize("p", [30, 100])
+def test_rbl_parity_cutoff_band(p):
+    """Pairs at r_c and r_s to within 1e-10 relative: N_s bit-exact and the forces against the
+    oracle, through the selection's FP64 decisions for the lanes inside its bands."""
+    pos, q, eps, sig, L, npl = _cutoff_band_system()
+    n = len(q)
+    alpha, rc, rs, seed, step = 0.06, 6.0, 12.0, 13, 4
+    note(f"case rbl cutoff band n={n} placed={npl} p={p}")
+    plan = RBLPlan(n, L, alpha, rc, rs, p, device=dev())
+    X = [to_dev(a) for a in (pos[:, 0], pos[:, 1], pos[:, 2], q, eps, sig)]
+    F, ns = plan.short_force(*X, seed=seed, step=step)
+    torch.cuda.synchronize()
+    F, ns = F.cpu().numpy(), ns.cpu().numpy()
+    F_ref, ns_ref = oracle.rbl_short_force(pos[:, 0], pos[:, 1], pos[:, 2], q, eps, sig, L, alpha, rc, rs, p,
+                                           oracle.rbl_offsets(seed, step, n))
+    assert np.array_equal(ns, ns_ref)
+    ef, em = force_err(F, F_ref), max_err(F, F_ref)
+    note(f"  force rel RMS {ef:.2e}, max {em:.2e}, N_s of the centres {ns[:npl:11].tolist()}")
+    assert ef < 1e-12 and em < 1e-11
     plan.close()
 
 
