@@ -165,22 +165,42 @@ __global__ __launch_bounds__(kRblBlock) void rbl_cell_kernel(const double* __res
   rank[i] = atomicAdd(&count[c], 1);
 }
 
+// Inclusive scan of v over the 64 lanes (lane i gets the sum over lanes 0 .. i).
+// Data-parallel-primitive moves: a scan within each row of 16 lanes (shifts right by 1, 2,
+// 4, 8, an empty source giving 0), then lane 15's sum added into rows 1 and 3 and lane 31's
+// into rows 2 and 3 (rows the mask leaves out add 0).
+__device__ inline int32_t wave_scan(int32_t v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);   // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);   // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);   // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);   // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+  return v;
+}
+
+// The sum of v over the 64 lanes, in every lane's hands.
+__device__ inline int32_t wave_sum(int32_t v) { return __builtin_amdgcn_readlane(wave_scan(v), 63); }
+
 // Exclusive scan of the cell counts in three launches: per-chunk totals, an in-order scan
-// of the totals (one block), then each chunk rescanned with its offset.
+// of the totals (one block), then each chunk rescanned with its offset.  Within a block:
+// each wave's scan, then the wave totals through LDS.
 __device__ inline int32_t block_exclusive_scan(int32_t v, int32_t* sh, int32_t* total) {
-  const int t = threadIdx.x;
-  sh[t] = v;
+  constexpr int kWaves = kRblBlock / 64;
+  const int32_t lane = (int32_t)(threadIdx.x & 63), wv = (int32_t)(threadIdx.x >> 6);
+  const int32_t incl = wave_scan(v);
+  if (lane == 63) sh[wv] = incl;
   __syncthreads();
-  for (int o = 1; o < kRblBlock; o <<= 1) {
-    const int32_t a = t >= o ? sh[t - o] : 0;
-    __syncthreads();
-    sh[t] += a;
-    __syncthreads();
+  int32_t off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k) {
+    const int32_t t = sh[k];
+    off += k < wv ? t : 0;
+    tot += t;
   }
-  const int32_t incl = sh[t];
-  *total = sh[kRblBlock - 1];
-  __syncthreads();
-  return incl - v;
+  __syncthreads();   // sh is written again by the next call
+  *total = tot;
+  return off + incl - v;
 }
 
 __global__ __launch_bounds__(kRblBlock) void rbl_scan_sums_kernel(const int32_t* __restrict__ count, int64_t ncell,
@@ -382,22 +402,6 @@ struct RblArgs {
 // The lanes of the wave whose p is true (a comparison straight into a lane mask).
 __device__ inline uint64_t wave_mask(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
-// Inclusive scan of v over the 64 lanes (lane i gets the sum over lanes 0 .. i).
-// Data-parallel-primitive moves: a scan within each row of 16 lanes (shifts right by 1, 2,
-// 4, 8, an empty source giving 0), then lane 15's sum added into rows 1 and 3 and lane 31's
-// into rows 2 and 3 (rows the mask leaves out add 0).
-__device__ inline int32_t wave_scan(int32_t v) {
-  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);   // row_shr:1
-  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);   // row_shr:2
-  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);   // row_shr:4
-  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);   // row_shr:8
-  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
-  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
-  return v;
-}
-
-// The sum of v over the 64 lanes, in every lane's hands.
-__device__ inline int32_t wave_sum(int32_t v) { return __builtin_amdgcn_readlane(wave_scan(v), 63); }
 
 __device__ inline int32_t lanes_below(uint64_t m) {
   return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
