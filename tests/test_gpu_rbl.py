@@ -8,7 +8,7 @@
     stencil is streamed in windows, r_c = r_s (no shell), 50 particles with p = 1, pairs at
     r_c and r_s to within 1e-10 (the FP64 decisions inside the selection's bands), a packed cluster whose particles have more pairs than the fast
     path's slots, and systems of 1, 2 and 7 particles (one in a box of mostly empty cells);
-  * the 1M-particle benchmark system: N_s exact and the raw force differences F_i - F_0 of
+  * the 1M-particle benchmark system and a 10M one: N_s exact and the raw force differences F_i - F_0 of
     sampled particles (the momentum correction is one vector for all) against the oracle's
     brute-force raw forces of those particles, and sum_i F_i = 0;
   * repeated calls are bitwise equal, and a new step gives a new batch.
@@ -222,12 +222,14 @@ def test_rbl_repeatable_and_step_dependent():
     plan.close()
 
 
-def test_rbl_1M_sampled():
-    """The benchmark system (1M particles, rc = 6, rs = 12, p = 30): N_s and raw force
-    differences of 200 sampled particles against the oracle, and zero total force."""
-    s = ri.primitive_electrolyte(1_000_000, 0.01, 1006)
+@pytest.mark.parametrize("n,seed_in", [(1_000_000, 1006), (10_000_000, 1007)])
+def test_rbl_large_sampled(n, seed_in):
+    """The benchmark system (1M particles, rc = 6, rs = 12, p = 30) and ten times it (10M,
+    166^3 cells, a 4 GB workspace): N_s and raw force differences of 200 sampled particles
+    against the oracle, and zero total force."""
+    s = ri.primitive_electrolyte(n, 0.01, seed_in)
     alpha, rc, rs, p, seed, step = 0.06, 6.0, 12.0, 30, 9, 4
-    note(f"case rbl 1M L={s.L:.2f}")
+    note(f"case rbl n={n} L={s.L:.2f}")
     plan, X, F, ns = _run(s, alpha, rc, rs, p, seed, step)
     sel = np.concatenate([[0], np.sort(np.random.default_rng(2).choice(np.arange(1, s.n), 199, replace=False))])
     raw, ns_ref = oracle.rbl_raw_subset(s.x, s.y, s.z, s.q, s.eps, s.sig, s.L, alpha, rc, rs, p, sel,
