@@ -47,11 +47,12 @@ struct RblGrid {
   double inv_nc, inv_nc2;   // 1 / nc, 1 / nc^2
 };
 
-// One particle in cell order: position and charge, sqrt(eps) and sigma; 48 bytes padded to
-// 64, so that a pair's data is one cache-line half.
+// One particle in cell order: position and charge, sqrt(eps) and sigma, and its batch offset
+// u_i; 56 bytes padded to 64, so that a pair's data is one cache-line half.
 struct alignas(64) RblRec {
   double4 pq;
   double2 lj;
+  double u;
 };
 static_assert(sizeof(RblRec) == 64, "RblRec is 64 bytes");
 
@@ -66,7 +67,6 @@ struct RblWs {
   uint4* fxa;        // N, in cell order: the position in 32-bit fixed point, frac(x / L) 2^32 (a
                      // wrapping difference is the minimum image), read by the selection
   int2* range;       // ncell: first and one-past-last cell-order position of each cell
-  double* ru;        // N, in cell order: the particle's batch offset u_i
   uint32_t* slot;    // Q pair entries per particle, interleaved (slot_index)
   int32_t* cnt;      // N, in cell order: pairs in the slot, -1 for the fallback
   int32_t* tns;      // N, in cell order: N_s
@@ -306,10 +306,10 @@ __global__ __launch_bounds__(kRblBlock) void rbl_gather_kernel(const double* __r
   RblRec r;
   r.pq = make_double4(x[i], y[i], z[i], q[i]);
   r.lj = make_double2(sqrt(eps[i]), sig[i]);
+  U64x4 ctr = {{(uint64_t)i, 0ull, 3ull, 0ull}};
+  r.u = u01_53(philox4x64_10(ctr, seed, step).v[0]);
   w.rec[t] = r;
   w.fxa[t] = make_uint4(fixed_coord(x[i], L), fixed_coord(y[i], L), fixed_coord(z[i], L), 0u);
-  U64x4 ctr = {{(uint64_t)i, 0ull, 3ull, 0ull}};
-  w.ru[t] = u01_53(philox4x64_10(ctr, seed, step).v[0]);
 }
 
 // Minimum-image difference a - b of one coordinate: d - L rint(d / L), with d / L taken as
@@ -525,7 +525,7 @@ __global__ __launch_bounds__(kRblBlock) __attribute__((amdgpu_waves_per_eu(8, 8)
 #pragma unroll
     for (int k = 0; k < kTgtGroup; ++k) {
       tf[k] = w.fxa[g0 + min(k, mg - 1)];
-      ug[k] = w.ru[g0 + min(k, mg - 1)];
+      ug[k] = w.rec[g0 + min(k, mg - 1)].u;
       cb[k] = sb[k] = ab[k] = 0;
     }
     int32_t un = lane < T ? list[lane] : -1;
@@ -747,7 +747,7 @@ __global__ __launch_bounds__(kRblBlock) void rbl_fallback_kernel(RblWs w, RblArg
     int32_t ns = 0;
     classified([&](int32_t, bool, bool shell) { ns += __popcll(wave_mask(shell)); });
     const bool sub = ns > a.p;
-    const double uoff = w.ru[t];
+    const double uoff = w.rec[t].u;
     const double wgt = sub ? (double)ns / (double)a.p : 1.0;
     const double slope = (double)a.p / (double)ns;
     const bool listed = sub && a.p <= kBatchCap;
@@ -906,7 +906,7 @@ void rbl_layout(rbl_plan* p) {
       sizeof(int32_t) * nc,        sizeof(int32_t) * n,            sizeof(int32_t) * (nc + 1),
       sizeof(int32_t) * (size_t)(p->nscan + 1), sizeof(int32_t) * n, sizeof(int32_t) * n,
       sizeof(RblRec) * n,          sizeof(uint4) * n,              sizeof(int2) * nc,
-      sizeof(double) * n,          sizeof(uint32_t) * 64 * ((n + 63) / 64) * (size_t)p->Q, sizeof(int32_t) * n,
+      1 /* unused */,              sizeof(uint32_t) * 64 * ((n + 63) / 64) * (size_t)p->Q, sizeof(int32_t) * n,
       sizeof(int32_t) * n,         sizeof(int32_t) * n,            sizeof(int32_t),
       sizeof(double) * 3 * kCorrBlocks, sizeof(double) * 3, sizeof(double) * kErfcMaxIntervals * kErfcCoef};
   size_t o = 0;
@@ -929,7 +929,6 @@ RblWs rbl_view(const rbl_plan* p, void* ws) {
   w.rec = reinterpret_cast<RblRec*>(b + p->off[6]);
   w.fxa = reinterpret_cast<uint4*>(b + p->off[7]);
   w.range = reinterpret_cast<int2*>(b + p->off[8]);
-  w.ru = reinterpret_cast<double*>(b + p->off[9]);
   w.slot = reinterpret_cast<uint32_t*>(b + p->off[10]);
   w.cnt = reinterpret_cast<int32_t*>(b + p->off[11]);
   w.tns = reinterpret_cast<int32_t*>(b + p->off[12]);
